@@ -1,0 +1,160 @@
+/*
+ * syk.h -- C interface of the MI355X (gfx950) SYK library.
+ *
+ * The library computes, on one GPU, the matrix-free product of the q=4 SYK
+ * Hamiltonian with state vectors and the Krylov-propagated correlators built
+ * on it, following arXiv:2002.05725:
+ *   H = sum_{i<j<k<l} J_ijkl chi_i chi_j chi_k chi_l            (main text, Eq. 1)
+ * with {chi_i, chi_j} = delta_ij and the Majoranas mapped to N/2 qubits by
+ * the Jordan-Wigner transformation of the SI (section "Jordan-Wigner
+ * transformation"): chi_i = 2^{-1/2} (prod_{q<k} Z_q) X_k for even i and
+ * 2^{-1/2} (prod_{q<k} Z_q) Y_k for odd i, k = floor(i/2), 0 <= i < N.
+ *
+ * Conventions shared by every call:
+ *  - States.  A state of N Majoranas has dim = 2^(N/2) complex entries.  Qubit
+ *    k is bit k of the basis index; Y = [[0,-i],[i,0]].  Entries are
+ *    interleaved (re, im) pairs: complex128 (SYK_C128) or complex64 (SYK_C64).
+ *  - Blocks.  nvec >= 1 states are stored as one row-major [dim][nvec]
+ *    array: entry (r, c) is element r*nvec + c.  nvec = 1 is a plain vector.
+ *    real_of_col (host, nvec entries, or NULL meaning all zeros) names the
+ *    coupling realisation used by each column.
+ *  - Couplings.  J holds n_real realisations back to back, each C(N,4) FP64
+ *    values for the quartets i<j<k<l in lexicographic order.
+ *  - Memory.  State pointers are device pointers owned by the caller, aligned
+ *    to 16 bytes; the library never frees them.  Scalar results go to host
+ *    pointers.  The handle owns its device tables and workspaces.
+ *  - Streams.  Device work is enqueued on `stream` (NULL = default stream).
+ *    Calls with host outputs synchronize that stream before returning.  One
+ *    handle serves one stream at a time: concurrent calls on one handle race
+ *    on its workspaces.
+ *  - Errors.  Nothing throws or aborts across this interface.  Any status
+ *    other than SYK_OK leaves outputs unspecified and handles valid;
+ *    syk_last_error() gives a message for the calling thread's last failure.
+ */
+#ifndef SYK_H
+#define SYK_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SYK_OK = 0,
+    SYK_EINVAL = 1,          /* invalid argument */
+    SYK_ENOMEM = 2,          /* device allocation failed */
+    SYK_EHIP = 3,            /* HIP runtime error */
+    SYK_EBREAKDOWN = 4,      /* non-finite norm inside a propagation */
+    SYK_ENOTCONVERGED = 5,   /* a-posteriori error estimate above the requested tolerance */
+    SYK_EUNSUPPORTED = 6     /* valid request this build does not handle */
+} syk_status;
+
+typedef enum { SYK_C128 = 0, SYK_C64 = 1 } syk_dtype;
+
+typedef struct syk_terms_s* syk_terms;
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char* syk_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int syk_version(void);
+
+/*
+ * Builds the Hamiltonian handle for N Majoranas (N even, 4 <= N <= 60) and
+ * n_real >= 1 coupling realisations (J: host, n_real * C(N,4) finite FP64,
+ * Eq. 1 with quartets in lexicographic order).  Each quartet becomes a Pauli
+ * string on N/2 qubits; strings are grouped by the set of qubits they flip,
+ * and the coefficient tables are uploaded to the current device.  *out must
+ * be released with syk_destroy_terms.
+ */
+syk_status syk_build_terms(int N, int n_real, const double* J, syk_terms* out);
+
+/* Releases the handle and every device buffer it owns.  NULL is accepted. */
+syk_status syk_destroy_terms(syk_terms t);
+
+/* Sizes of a handle; any output pointer may be NULL.  n_masks is the number
+ * of distinct qubit-flip patterns (C(M,4) + C(M,2) + 1 for M = N/2 qubits). */
+syk_status syk_terms_info(syk_terms t, int* N, int* n_real, int64_t* dim, int64_t* n_terms,
+                          int64_t* n_masks);
+
+/*
+ * out = H psi column by column (matrix-free product, SI "Krylov subspace
+ * methods": the product is formed on the fly from the symbolic terms).
+ * psi, out: device [dim][nvec] of `dtype`; out must not overlap psi.
+ * Column c uses realisation real_of_col[c].  complex64 stores and multiplies
+ * in FP32 and sums each row in FP64 across flip groups.
+ */
+syk_status syk_apply_H(syk_terms t, syk_dtype dtype, int nvec, const int32_t* real_of_col,
+                       const void* psi, void* out, hipStream_t stream);
+
+/* out = chi_a psi for one Majorana 0 <= a < N (SI Jordan-Wigner map), every
+ * column.  out must not overlap psi. */
+syk_status syk_apply_majorana(syk_terms t, syk_dtype dtype, int a, int nvec, const void* psi,
+                              void* out, hipStream_t stream);
+
+/* Column-wise <a_c | b_c> accumulated in FP64 with a fixed reduction order
+ * (bitwise reproducible run to run).  out: host, nvec (re, im) pairs. */
+syk_status syk_dot(syk_dtype dtype, int64_t dim, int nvec, const void* a, const void* b,
+                   double* out, hipStream_t stream);
+
+/* Krylov options.  m: basis vectors per step (2..64).  dt: real-time step
+ * length.  tau_step: imaginary-time step length.  tol: if > 0, a step whose
+ * a-posteriori error estimate exceeds tol makes the call return
+ * SYK_ENOTCONVERGED (the result is still written). */
+typedef struct {
+    int m;
+    double dt;
+    double tau_step;
+    double tol;
+} syk_krylov_opts;
+
+/*
+ * psi <- exp(total * (z_re + i z_im) * H) psi, column by column, by Lanczos
+ * steps (SI "Krylov subspace methods"): each step builds an m-vector Krylov
+ * basis with two passes of classical Gram-Schmidt (FP64 inner products),
+ * exponentiates the m x m tridiagonal projection in FP64 on the host, and
+ * combines the basis.  The step length is dt for z_re == 0 and tau_step
+ * otherwise; total >= 0 is cut into equal steps no longer than that.  A
+ * Krylov space that becomes invariant ends the step early with the exact
+ * result.  err_est (host, nvec, may be NULL) receives the largest step error
+ * estimate beta_m |e_m^T e^{zT} e_1| ||psi|| per column.
+ */
+syk_status syk_krylov_expmv(syk_terms t, syk_dtype dtype, int nvec, const int32_t* real_of_col,
+                            double z_re, double z_im, double total, const syk_krylov_opts* opts,
+                            void* psi_inout, double* err_est, hipStream_t stream);
+
+/*
+ * Two-point function from a typical state (main text Eq. 2-3 with the
+ * typicality formula of SI "Disorder averaging"):
+ *   G(t) = <psi| rho^{1/2} chi_i(t) chi_i rho^{1/2} |psi> / Z,
+ *   Z = <psi|rho|psi>, rho = e^{-beta H}, chi(t) = e^{iHt} chi e^{-iHt}.
+ * t: host, nt >= 1 ascending values >= 0.  psi0: device [dim][nvec].
+ * G: host [nt][nvec] (re, im) pairs; G_R(t) = 2 Re G.  Z: host [nvec] or NULL.
+ */
+syk_status syk_two_point(syk_terms t, syk_dtype dtype, int i, double beta, const double* times,
+                         int nt, int nvec, const int32_t* real_of_col, const void* psi0,
+                         const syk_krylov_opts* opts, double* G, double* Z, hipStream_t stream);
+
+/*
+ * Regularized OTOC (main text Eq. 4) from a typical state, i != j:
+ *   F(t) = Re <A^dag psi | A psi> / <psi|rho|psi>,
+ *   A = rho^{1/8} chi_i(t) rho^{1/4} chi_j rho^{1/8},  rho = e^{-beta H},
+ * i.e. Tr[...] in Eq. 4 is replaced by <psi|...|psi> (SI "Disorder
+ * averaging") with the trace cut symmetrically.  Forward legs e^{-iHt} are
+ * advanced incrementally from one output time to the next; each output time
+ * then propagates back by its full t.
+ * t: host, nt >= 1 ascending values >= 0.  psi0: device [dim][nvec].
+ * F: host [nt][nvec]; F_im (may be NULL): the imaginary part, a typicality
+ * diagnostic; Z: host [nvec] or NULL.
+ */
+syk_status syk_otoc(syk_terms t, syk_dtype dtype, int i, int j, double beta, const double* times,
+                    int nt, int nvec, const int32_t* real_of_col, const void* psi0,
+                    const syk_krylov_opts* opts, double* F, double* F_im, double* Z,
+                    hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SYK_H */

@@ -1,0 +1,181 @@
+"""Python binding of the SYK library: the C calls of include/syk.h with torch
+tensors for device memory and streams.  Argument marshalling only; every step
+of the computation runs in the HIP library.
+
+States are complex torch tensors on the GPU, shape [dim] (one vector) or
+[dim, nvec] (a block, row-major as the library expects).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import KrylovOpts, check, lib
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.complex128:
+        return _lib.SYK_C128
+    if t.dtype == torch.complex64:
+        return _lib.SYK_C64
+    raise TypeError(f"states must be complex128 or complex64, got {t.dtype}")
+
+
+def _nvec(t: torch.Tensor) -> int:
+    if t.dim() == 1:
+        return 1
+    if t.dim() == 2:
+        return int(t.shape[1])
+    raise ValueError("states must have shape [dim] or [dim, nvec]")
+
+
+def _check_state(t: torch.Tensor, dim: int, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.shape[0] != dim:
+        raise ValueError(f"{name} has {t.shape[0]} rows, expected {dim}")
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _real_arr(real_of_col, nvec):
+    if real_of_col is None:
+        return None, None
+    a = np.ascontiguousarray(real_of_col, dtype=np.int32)
+    if a.shape != (nvec,):
+        raise ValueError("real_of_col must have one entry per column")
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _opts(m, dt, tau_step, tol):
+    return KrylovOpts(int(m), float(dt), float(tau_step), float(tol))
+
+
+class Terms:
+    """Hamiltonian handle (syk_build_terms): N Majoranas, one or more coupling
+    realisations J of shape [C(N,4)] or [n_real, C(N,4)] (FP64, lexicographic)."""
+
+    def __init__(self, N: int, J):
+        J = np.ascontiguousarray(J, dtype=np.float64)
+        n_real = 1 if J.ndim == 1 else J.shape[0]
+        h = ctypes.c_void_p()
+        check(lib().syk_build_terms(int(N), int(n_real), J.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)),
+              "syk_build_terms")
+        self._h = h
+        self.N = N
+        self.n_real = n_real
+        Nn, nr = ctypes.c_int(), ctypes.c_int()
+        d, nt, nm = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(lib().syk_terms_info(h, ctypes.byref(Nn), ctypes.byref(nr), ctypes.byref(d), ctypes.byref(nt),
+                                   ctypes.byref(nm)), "syk_terms_info")
+        self.dim, self.n_terms, self.n_masks = d.value, nt.value, nm.value
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("Terms handle already closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().syk_destroy_terms(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_terms(N: int, J) -> Terms:
+    return Terms(N, J)
+
+
+def apply_H(terms: Terms, psi: torch.Tensor, out: torch.Tensor | None = None, real_of_col=None) -> torch.Tensor:
+    _check_state(psi, terms.dim, "psi")
+    nvec = _nvec(psi)
+    if out is None:
+        out = torch.empty_like(psi)
+    _check_state(out, terms.dim, "out")
+    ra, rp = _real_arr(real_of_col, nvec)
+    check(lib().syk_apply_H(terms.handle, _dtype_code(psi), nvec, rp, ctypes.c_void_p(psi.data_ptr()),
+                            ctypes.c_void_p(out.data_ptr()), _stream()), "syk_apply_H")
+    return out
+
+
+def apply_majorana(terms: Terms, a: int, psi: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    _check_state(psi, terms.dim, "psi")
+    if out is None:
+        out = torch.empty_like(psi)
+    check(lib().syk_apply_majorana(terms.handle, _dtype_code(psi), int(a), _nvec(psi),
+                                   ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream()),
+          "syk_apply_majorana")
+    return out
+
+
+def dot(a: torch.Tensor, b: torch.Tensor) -> np.ndarray:
+    """Column-wise <a|b> (FP64 accumulation), complex numpy array [nvec]."""
+    if a.shape != b.shape or a.dtype != b.dtype:
+        raise ValueError("a and b must have equal shape and dtype")
+    nvec = _nvec(a)
+    out = np.empty(2 * nvec, dtype=np.float64)
+    check(lib().syk_dot(_dtype_code(a), int(a.shape[0]), nvec, ctypes.c_void_p(a.data_ptr()),
+                        ctypes.c_void_p(b.data_ptr()), out.ctypes.data_as(ctypes.c_void_p), _stream()), "syk_dot")
+    return out[0::2] + 1j * out[1::2]
+
+
+def krylov_expmv(terms: Terms, psi: torch.Tensor, z: complex, total: float, m: int = 20, dt: float = 0.1,
+                 tau_step: float = 0.1, tol: float = 0.0, real_of_col=None) -> np.ndarray:
+    """psi <- exp(total * z * H) psi in place; returns the per-column error estimate."""
+    _check_state(psi, terms.dim, "psi")
+    nvec = _nvec(psi)
+    ra, rp = _real_arr(real_of_col, nvec)
+    err = np.zeros(nvec)
+    o = _opts(m, dt, tau_step, tol)
+    check(lib().syk_krylov_expmv(terms.handle, _dtype_code(psi), nvec, rp, float(np.real(z)), float(np.imag(z)),
+                                 float(total), ctypes.byref(o), ctypes.c_void_p(psi.data_ptr()),
+                                 err.ctypes.data_as(ctypes.c_void_p), _stream()), "syk_krylov_expmv")
+    return err
+
+
+def two_point(terms: Terms, i: int, beta: float, times, psi0: torch.Tensor, m: int = 20, dt: float = 0.1,
+              tau_step: float = 0.1, real_of_col=None):
+    """G(t) (complex [nt, nvec]) and Z ([nvec]); see syk_two_point."""
+    _check_state(psi0, terms.dim, "psi0")
+    nvec = _nvec(psi0)
+    t = np.ascontiguousarray(times, dtype=np.float64)
+    G = np.empty((t.size, nvec, 2))
+    Z = np.empty(nvec)
+    ra, rp = _real_arr(real_of_col, nvec)
+    o = _opts(m, dt, tau_step, 0.0)
+    check(lib().syk_two_point(terms.handle, _dtype_code(psi0), int(i), float(beta),
+                              t.ctypes.data_as(ctypes.c_void_p), t.size, nvec, rp, ctypes.c_void_p(psi0.data_ptr()),
+                              ctypes.byref(o), G.ctypes.data_as(ctypes.c_void_p), Z.ctypes.data_as(ctypes.c_void_p),
+                              _stream()), "syk_two_point")
+    return G[..., 0] + 1j * G[..., 1], Z
+
+
+def otoc(terms: Terms, i: int, j: int, beta: float, times, psi0: torch.Tensor, m: int = 20, dt: float = 0.1,
+         tau_step: float = 0.1, tol: float = 0.0, real_of_col=None):
+    """F(t) ([nt, nvec]), Im part ([nt, nvec]) and Z ([nvec]); see syk_otoc."""
+    _check_state(psi0, terms.dim, "psi0")
+    nvec = _nvec(psi0)
+    t = np.ascontiguousarray(times, dtype=np.float64)
+    F = np.empty((t.size, nvec))
+    Fi = np.empty((t.size, nvec))
+    Z = np.empty(nvec)
+    ra, rp = _real_arr(real_of_col, nvec)
+    o = _opts(m, dt, tau_step, tol)
+    check(lib().syk_otoc(terms.handle, _dtype_code(psi0), int(i), int(j), float(beta),
+                         t.ctypes.data_as(ctypes.c_void_p), t.size, nvec, rp, ctypes.c_void_p(psi0.data_ptr()),
+                         ctypes.byref(o), F.ctypes.data_as(ctypes.c_void_p), Fi.ctypes.data_as(ctypes.c_void_p),
+                         Z.ctypes.data_as(ctypes.c_void_p), _stream()), "syk_otoc")
+    return F, Fi, Z

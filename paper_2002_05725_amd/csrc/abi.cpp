@@ -1,0 +1,298 @@
+// C-ABI entry points: argument validation, error capture, dispatch.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "estimators.hpp"
+
+using namespace syk;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename F>
+syk_status guard(F&& f)
+{
+    try {
+        f();
+        g_last_error.clear();
+        return SYK_OK;
+    } catch (const Error& e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return SYK_ENOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return SYK_EINVAL;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return SYK_EINVAL;
+    }
+}
+
+void check_handle(syk_terms t) { require(t != nullptr && t->H.masks != nullptr, "invalid syk_terms handle"); }
+
+void check_dtype(syk_dtype d) { require(d == SYK_C128 || d == SYK_C64, "dtype must be SYK_C128 or SYK_C64"); }
+
+void check_block(syk_terms t, int nvec, const int32_t* real)
+{
+    require(nvec >= 1, "nvec must be >= 1");
+    if (real)
+        for (int c = 0; c < nvec; ++c)
+            require(real[c] >= 0 && real[c] < t->host.n_real, "real_of_col entry out of range");
+}
+
+void check_ptr(const void* p, const char* what)
+{
+    require(p != nullptr, std::string(what) + " is NULL");
+    require(((uintptr_t)p & 15u) == 0, std::string(what) + " is not 16-byte aligned");
+}
+
+void check_no_overlap(const void* a, const void* b, size_t bytes)
+{
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    require(x + bytes <= y || y + bytes <= x, "input and output buffers overlap");
+}
+
+syk_krylov_opts check_opts(const syk_krylov_opts* o)
+{
+    require(o != nullptr, "Krylov options are NULL");
+    require(o->m >= 2 && o->m <= 64, "Krylov m must be in [2, 64]");
+    require(std::isfinite(o->dt) && o->dt > 0, "Krylov dt must be > 0");
+    require(std::isfinite(o->tau_step) && o->tau_step > 0, "Krylov tau_step must be > 0");
+    return *o;
+}
+
+template <typename T>
+void upload(DevBuf& b, const std::vector<T>& v)
+{
+    b.ensure(std::max<size_t>(v.size() * sizeof(T), 16));
+    if (!v.empty()) SYK_HIP(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+template <typename T>
+std::vector<T> narrow(const std::vector<T>& v) { return v; }
+
+std::vector<c64> to_c64(const std::vector<c128>& v)
+{
+    std::vector<c64> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = {(float)v[i].re, (float)v[i].im};
+    return o;
+}
+
+std::vector<float> to_f32(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
+
+}  // namespace
+
+namespace syk {
+
+const Group* HamiltonianDev::groups_for(int tile_bits) const
+{
+    auto it = groups.find(tile_bits);
+    if (it == groups.end()) {
+        std::vector<Group> g = make_groups(*host_masks, tile_bits);
+        std::unique_ptr<DevBuf> b(new DevBuf());
+        upload(*b, g);
+        n_groups[tile_bits] = (int)g.size();
+        it = groups.emplace(tile_bits, std::move(b)).first;
+    }
+    return it->second->as<Group>();
+}
+
+int HamiltonianDev::n_groups_for(int tile_bits) const
+{
+    groups_for(tile_bits);
+    return n_groups.at(tile_bits);
+}
+
+}  // namespace syk
+
+extern "C" {
+
+const char* syk_last_error(void) { return g_last_error.c_str(); }
+
+int syk_version(void) { return 100; }
+
+syk_status syk_build_terms(int N, int n_real, const double* J, syk_terms* out)
+{
+    return guard([&] {
+        require(out != nullptr, "out is NULL");
+        *out = nullptr;
+        require(N >= 4 && N <= 60 && N % 2 == 0, "N must be even with 4 <= N <= 60");
+        require(n_real >= 1, "n_real must be >= 1");
+        require(J != nullptr, "J is NULL");
+        const int64_t nq = (int64_t)N * (N - 1) * (N - 2) * (N - 3) / 24;
+        for (int64_t k = 0; k < nq * n_real; ++k) require(std::isfinite(J[k]), "J holds a non-finite value");
+        std::unique_ptr<syk_terms_s> h(new syk_terms_s());
+        SYK_HIP(hipGetDevice(&h->device));
+        build_tables(N, n_real, J, h->host);
+        const TermTables& T = h->host;
+        DeviceTerms& d = h->dev;
+        upload(d.masks, T.masks);
+        upload(d.tab4_d, T.tab4);
+        upload(d.tab4_f, to_c64(T.tab4));
+        upload(d.phi2_d, T.phi2);
+        upload(d.phi2_f, to_c64(T.phi2));
+        upload(d.w2_d, T.w2);
+        upload(d.w2_f, to_f32(T.w2));
+        upload(d.dz, T.dz);
+        upload(d.dw_d, T.dw);
+        upload(d.dw_f, to_f32(T.dw));
+        HamiltonianDev& H = h->H;
+        H.N = N;
+        H.M = N / 2;
+        H.n_real = n_real;
+        H.n_diag = T.n_diag;
+        H.masks = d.masks.as<MaskRec>();
+        H.tab4_d = d.tab4_d.as<c128>();
+        H.tab4_f = d.tab4_f.as<c64>();
+        H.phi2_d = d.phi2_d.as<c128>();
+        H.phi2_f = d.phi2_f.as<c64>();
+        H.w2_d = d.w2_d.as<double>();
+        H.w2_f = d.w2_f.as<float>();
+        H.dz = d.dz.as<uint32_t>();
+        H.dw_d = d.dw_d.as<double>();
+        H.dw_f = d.dw_f.as<float>();
+        H.host_masks = &T.masks;
+        *out = h.release();
+    });
+}
+
+syk_status syk_destroy_terms(syk_terms t)
+{
+    return guard([&] { delete t; });
+}
+
+syk_status syk_terms_info(syk_terms t, int* N, int* n_real, int64_t* dim, int64_t* n_terms, int64_t* n_masks)
+{
+    return guard([&] {
+        check_handle(t);
+        if (N) *N = t->H.N;
+        if (n_real) *n_real = t->H.n_real;
+        if (dim) *dim = (int64_t)1 << t->H.M;
+        if (n_terms) *n_terms = t->host.n_terms;
+        if (n_masks) *n_masks = (int64_t)t->host.masks.size();
+    });
+}
+
+syk_status syk_apply_H(syk_terms t, syk_dtype dtype, int nvec, const int32_t* real_of_col, const void* psi,
+                       void* out, hipStream_t stream)
+{
+    return guard([&] {
+        check_handle(t);
+        check_dtype(dtype);
+        check_block(t, nvec, real_of_col);
+        check_ptr(psi, "psi");
+        check_ptr(out, "out");
+        const size_t bytes = ((size_t)1 << t->H.M) * nvec * elem_bytes(dtype);
+        check_no_overlap(psi, out, bytes);
+        ApplyPlan P = plan_apply(t->H.M, nvec, dtype, nullptr);
+        launch_apply_h(t->H, dtype, nvec, real_of_col, psi, out, P, stream);
+    });
+}
+
+syk_status syk_apply_majorana(syk_terms t, syk_dtype dtype, int a, int nvec, const void* psi, void* out,
+                              hipStream_t stream)
+{
+    return guard([&] {
+        check_handle(t);
+        check_dtype(dtype);
+        require(a >= 0 && a < t->H.N, "Majorana index out of range");
+        require(nvec >= 1, "nvec must be >= 1");
+        check_ptr(psi, "psi");
+        check_ptr(out, "out");
+        VecOps ops(*t, dtype, (int64_t)1 << t->H.M, nvec, stream);
+        check_no_overlap(psi, out, ops.vec_bytes());
+        ops.majorana(a, psi, out);
+    });
+}
+
+syk_status syk_dot(syk_dtype dtype, int64_t dim, int nvec, const void* a, const void* b, double* out,
+                   hipStream_t stream)
+{
+    return guard([&] {
+        check_dtype(dtype);
+        require(dim >= 1 && nvec >= 1, "dim and nvec must be >= 1");
+        check_ptr(a, "a");
+        check_ptr(b, "b");
+        require(out != nullptr, "out is NULL");
+        // Workspace owner for handle-free reductions; kept until the process
+        // ends so no device memory is freed during thread teardown.
+        static thread_local syk_terms_s* scratch = new syk_terms_s();
+        VecOps ops(*scratch, dtype, dim, nvec, stream);
+        std::vector<zd> d = ops.multidot(a, 1, b);
+        for (int c = 0; c < nvec; ++c) {
+            out[2 * c] = d[c].real();
+            out[2 * c + 1] = d[c].imag();
+        }
+    });
+}
+
+syk_status syk_krylov_expmv(syk_terms t, syk_dtype dtype, int nvec, const int32_t* real_of_col, double z_re,
+                            double z_im, double total, const syk_krylov_opts* opts, void* psi_inout,
+                            double* err_est, hipStream_t stream)
+{
+    return guard([&] {
+        check_handle(t);
+        check_dtype(dtype);
+        check_block(t, nvec, real_of_col);
+        syk_krylov_opts o = check_opts(opts);
+        check_ptr(psi_inout, "psi");
+        require(std::isfinite(z_re) && std::isfinite(z_im) && std::isfinite(total) && total >= 0,
+                "z and total must be finite, total >= 0");
+        BlockCtx c(*t, dtype, nvec, real_of_col, stream);
+        KrylovStats st;
+        st.err.assign(nvec, 0.0);
+        const double step = (z_re == 0.0) ? o.dt : o.tau_step;
+        krylov_propagate(c, psi_inout, std::complex<double>(z_re, z_im), total, step, o.m, st);
+        SYK_HIP(hipStreamSynchronize(stream));
+        if (err_est)
+            for (int k = 0; k < nvec; ++k) err_est[k] = st.err[k];
+        if (o.tol > 0)
+            for (double e : st.err)
+                if (e > o.tol) throw Error(SYK_ENOTCONVERGED, "Krylov error estimate above tolerance");
+    });
+}
+
+syk_status syk_two_point(syk_terms t, syk_dtype dtype, int i, double beta, const double* times, int nt, int nvec,
+                         const int32_t* real_of_col, const void* psi0, const syk_krylov_opts* opts, double* G,
+                         double* Z, hipStream_t stream)
+{
+    return guard([&] {
+        check_handle(t);
+        check_dtype(dtype);
+        check_block(t, nvec, real_of_col);
+        syk_krylov_opts o = check_opts(opts);
+        require(i >= 0 && i < t->H.N, "Majorana index out of range");
+        require(std::isfinite(beta) && beta >= 0, "beta must be finite and >= 0");
+        check_ptr(psi0, "psi0");
+        require(G != nullptr, "G is NULL");
+        BlockCtx c(*t, dtype, nvec, real_of_col, stream);
+        two_point(c, i, beta, times, nt, psi0, o, G, Z);
+    });
+}
+
+syk_status syk_otoc(syk_terms t, syk_dtype dtype, int i, int j, double beta, const double* times, int nt, int nvec,
+                    const int32_t* real_of_col, const void* psi0, const syk_krylov_opts* opts, double* F,
+                    double* F_im, double* Z, hipStream_t stream)
+{
+    return guard([&] {
+        check_handle(t);
+        check_dtype(dtype);
+        check_block(t, nvec, real_of_col);
+        syk_krylov_opts o = check_opts(opts);
+        require(i >= 0 && i < t->H.N && j >= 0 && j < t->H.N, "Majorana index out of range");
+        require(i != j, "the OTOC needs i != j");
+        require(std::isfinite(beta) && beta >= 0, "beta must be finite and >= 0");
+        check_ptr(psi0, "psi0");
+        require(F != nullptr, "F is NULL");
+        BlockCtx c(*t, dtype, nvec, real_of_col, stream);
+        otoc(c, i, j, beta, times, nt, psi0, o, F, F_im, Z);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,16 @@
+// Typical-state correlators built on the Krylov propagator.
+#pragma once
+
+#include "krylov.hpp"
+
+namespace syk {
+
+// G[k][c] (re, im) = <psi|rho^{1/2} chi_i(t_k) chi_i rho^{1/2}|psi> / Z_c
+void two_point(BlockCtx& c, int i, double beta, const double* t, int nt, const void* psi0,
+               const syk_krylov_opts& o, double* G, double* Z);
+
+// F[k][c] = Re <A^dag psi|A psi> / <psi|rho|psi>, A = rho^{1/8} chi_i(t) rho^{1/4} chi_j rho^{1/8}
+void otoc(BlockCtx& c, int i, int j, double beta, const double* t, int nt, const void* psi0,
+          const syk_krylov_opts& o, double* F, double* F_im, double* Z);
+
+}  // namespace syk

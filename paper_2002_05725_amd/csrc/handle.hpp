@@ -1,0 +1,55 @@
+// The syk_terms handle: host tables, device tables and workspaces.
+#pragma once
+
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "terms.hpp"
+
+namespace syk {
+
+// Device view of the Hamiltonian tables used by the kernels.
+struct HamiltonianDev {
+    int N = 0, M = 0, n_real = 0, n_diag = 0;
+    const MaskRec* masks = nullptr;
+    const c128* tab4_d = nullptr;
+    const c64* tab4_f = nullptr;
+    const c128* phi2_d = nullptr;
+    const c64* phi2_f = nullptr;
+    const double* w2_d = nullptr;
+    const float* w2_f = nullptr;
+    const uint32_t* dz = nullptr;
+    const double* dw_d = nullptr;
+    const float* dw_f = nullptr;
+    // Group lists for each tile size, built on first use.
+    const std::vector<MaskRec>* host_masks = nullptr;
+    mutable std::map<int, std::unique_ptr<DevBuf>> groups;
+    mutable std::map<int, int> n_groups;
+    const Group* groups_for(int tile_bits) const;
+    int n_groups_for(int tile_bits) const;
+};
+
+// Named device workspaces, grown on demand and kept until the handle dies.
+struct Workspace {
+    std::map<std::string, std::unique_ptr<DevBuf>> bufs;
+    void* get(const std::string& name, size_t bytes)
+    {
+        auto& b = bufs[name];
+        if (!b) b.reset(new DevBuf());
+        b->ensure(bytes);
+        return b->p;
+    }
+    void release_all() { bufs.clear(); }
+};
+
+}  // namespace syk
+
+struct syk_terms_s {
+    int device = 0;
+    syk::TermTables host;
+    syk::DeviceTerms dev;
+    syk::HamiltonianDev H;
+    syk::Workspace ws;
+    unsigned upload_slot = 0;       // ring position of small coefficient uploads
+};

@@ -1,0 +1,43 @@
+// Krylov (Lanczos) propagation on top of apply_H.
+#pragma once
+
+#include <complex>
+#include <vector>
+
+#include "apply_h.hpp"
+#include "vec.hpp"
+
+namespace syk {
+
+// Everything a propagation needs for one block of columns.
+struct BlockCtx {
+    syk_terms_s& h;
+    syk_dtype dtype;
+    int nvec;
+    const int32_t* real_of_col;   // host or NULL
+    hipStream_t stream;
+    ApplyPlan plan;
+    VecOps ops;
+
+    BlockCtx(syk_terms_s& h_, syk_dtype dt, int nvec_, const int32_t* real, hipStream_t s);
+    int64_t dim() const { return (int64_t)1 << h.H.M; }
+    void apply_H(const void* in, void* out);
+};
+
+struct KrylovStats {
+    std::vector<double> err;   // largest step error estimate per column
+    int steps = 0;
+};
+
+// Eigen-decomposition of a real symmetric n x n matrix (row-major a, destroyed):
+// eigenvalues in w, eigenvectors as columns of v (row-major n x n).
+void symmetric_eig(int n, std::vector<double>& a, std::vector<double>& w, std::vector<double>& v);
+
+// psi <- exp(z H) psi per column with one Lanczos step of m vectors.
+void krylov_step(BlockCtx& c, void* psi, std::complex<double> z, int m, KrylovStats& st);
+
+// psi <- exp(total * z H) psi in ceil(total / step) equal steps (total >= 0).
+void krylov_propagate(BlockCtx& c, void* psi, std::complex<double> z, double total, double step, int m,
+                      KrylovStats& st);
+
+}  // namespace syk

@@ -1,0 +1,173 @@
+// Term builder.  Each coupling J_ijkl of Eq. 1 multiplies chi_i chi_j chi_k chi_l;
+// under the Jordan-Wigner map of the SI this product is one Pauli string
+// (1/4) i^ph X^x Z^z.  Terms are grouped by their flip mask x: every mask has
+// even weight (the SI's conserved fermion parity) and |x| is 4, 2 or 0.
+#include "terms.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <unordered_map>
+
+namespace syk {
+
+namespace {
+
+struct Term {
+    Pauli p;
+    int64_t n;   // coupling index
+};
+
+inline std::complex<double> iphase(int ph)
+{
+    static const std::complex<double> v[4] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+    return v[ph & 3];
+}
+
+void fail(const std::string& m) { throw Error(SYK_EUNSUPPORTED, "term structure: " + m); }
+
+}  // namespace
+
+void build_tables(int N, int n_real, const double* J, TermTables& T)
+{
+    const int M = N / 2;
+    T.N = N;
+    T.M = M;
+    T.n_real = n_real;
+
+    Pauli chi[64];
+    for (int a = 0; a < N; ++a) chi[a] = majorana_pauli(a);
+
+    // Every quartet as a Pauli string, bucketed by flip mask.
+    std::unordered_map<uint32_t, std::vector<Term>> by_x;
+    int64_t n = 0;
+    for (int i = 0; i < N; ++i)
+        for (int j = i + 1; j < N; ++j)
+            for (int k = j + 1; k < N; ++k)
+                for (int l = k + 1; l < N; ++l, ++n) {
+                    Pauli p = pauli_mul(pauli_mul(chi[i], chi[j]), pauli_mul(chi[k], chi[l]));
+                    by_x[p.x].push_back({p, n});
+                }
+    T.n_terms = n;
+
+    std::vector<uint32_t> xs;
+    xs.reserve(by_x.size());
+    for (auto& kv : by_x) xs.push_back(kv.first);
+    std::sort(xs.begin(), xs.end());
+
+    T.masks.clear();
+    T.tab4.clear();
+    T.phi2.clear();
+    T.w2.clear();
+    T.dz.clear();
+    T.dw.clear();
+    T.n_quad = T.n_pair = T.n_diag = 0;
+
+    const size_t NQ = (size_t)n;
+    auto coef = [&](const Term& t, int r) {   // J * i^ph / 4 for realisation r
+        return J[(size_t)r * NQ + t.n] * 0.25 * iphase(t.p.ph);
+    };
+
+    for (uint32_t x : xs) {
+        const std::vector<Term>& ts = by_x[x];
+        const int w = __builtin_popcount(x);
+        MaskRec rec{};
+        rec.x = x;
+        int qn = 0;
+        for (int b = 0; b < M; ++b)
+            if (x >> b & 1u) rec.q[qn++] = (uint8_t)b;
+
+        if (w == 4) {
+            // All 16 terms share their Z string outside the flipped qubits.
+            if (ts.size() != 16) fail("weight-4 mask without 16 terms");
+            uint32_t zb = ts[0].p.z & ~x;
+            for (const Term& t : ts)
+                if ((t.p.z & ~x) != zb) fail("weight-4 mask with differing Z strings");
+            rec.zbase = zb;
+            rec.type_tab = (uint32_t)MASK_QUAD << 28 | (uint32_t)T.n_quad;
+            // T[idx]: idx bit m = bit q_m of the output row r; the source row
+            // s = r ^ x has the opposite bits there.
+            for (int r = 0; r < n_real; ++r)
+                for (int idx = 0; idx < 16; ++idx) {
+                    uint32_t s_loc = 0;
+                    for (int m = 0; m < 4; ++m)
+                        if (!((idx >> m) & 1)) s_loc |= 1u << rec.q[m];
+                    std::complex<double> acc = 0.0;
+                    for (const Term& t : ts) {
+                        double sg = (__builtin_popcount(s_loc & t.p.z) & 1) ? -1.0 : 1.0;
+                        acc += sg * coef(t, r);
+                    }
+                    T.tab4.push_back({acc.real(), acc.imag()});
+                }
+            ++T.n_quad;
+        } else if (w == 2) {
+            // Terms chi_A chi_B chi_2c chi_2c+1: Z string = zbase ^ (bits at
+            // q0, q1) ^ (1 << c), with c not flipped.  e = (z_q0, z_q1).
+            const uint32_t qa = rec.q[0], qb = rec.q[1];
+            // chi_A chi_B contributes the Z string on the qubits strictly
+            // between q0 and q1 (plus bits at q0, q1); the pair adds Z_c.
+            // Checked term by term below.
+            const uint32_t zb = ((1u << qb) - 1u) & ~((1u << (qa + 1)) - 1u);
+            rec.zbase = zb;
+            rec.type_tab = (uint32_t)MASK_PAIR << 28 | (uint32_t)T.n_pair;
+            // Phase class of each e must be uniform (real or imaginary).
+            int cls[4] = {-1, -1, -1, -1};
+            std::vector<double> wts((size_t)n_real * 4 * (M + 1), 0.0);
+            for (const Term& t : ts) {
+                uint32_t extra = (t.p.z & ~x) ^ zb;
+                if (__builtin_popcount(extra) != 1 || (extra & x)) fail("weight-2 term without a single Z_c");
+                int c = __builtin_ctz(extra);
+                int e = (int)((t.p.z >> qa) & 1u) | (int)((t.p.z >> qb) & 1u) << 1;
+                int c_cls = t.p.ph & 1;              // 0: real phase, 1: imaginary
+                double sgn = (t.p.ph & 2) ? -1.0 : 1.0;
+                if (cls[e] < 0) cls[e] = c_cls;
+                if (cls[e] != c_cls) fail("weight-2 mask with mixed phase class");
+                for (int r = 0; r < n_real; ++r) {
+                    double v = J[(size_t)r * NQ + t.n] * 0.25 * sgn;
+                    // sigma_c = 1 - 2 r_c:  v sigma_c = v - 2 v r_c
+                    wts[((size_t)r * 4 + e) * (M + 1) + M] += v;
+                    wts[((size_t)r * 4 + e) * (M + 1) + c] += -2.0 * v;
+                }
+            }
+            // Phi[idx][e] = i^cls_e (-1)^{s_q0 e_0 + s_q1 e_1}, s = opposite of r's bits.
+            for (int idx = 0; idx < 4; ++idx)
+                for (int e = 0; e < 4; ++e) {
+                    int sa = !((idx >> 0) & 1), sb = !((idx >> 1) & 1);
+                    double sg = (((sa & (e & 1)) ^ (sb & (e >> 1))) & 1) ? -1.0 : 1.0;
+                    std::complex<double> ph = (cls[e] == 1) ? std::complex<double>(0, sg)
+                                                            : std::complex<double>(sg, 0);
+                    if (cls[e] < 0) ph = 0.0;
+                    T.phi2.push_back({ph.real(), ph.imag()});
+                }
+            T.w2.insert(T.w2.end(), wts.begin(), wts.end());
+            ++T.n_pair;
+        } else if (w == 0) {
+            rec.zbase = 0;
+            rec.type_tab = (uint32_t)MASK_DIAG << 28;
+            T.n_diag = (int)ts.size();
+            T.dz.resize(ts.size());
+            T.dw.assign((size_t)n_real * ts.size(), 0.0);
+            for (size_t m = 0; m < ts.size(); ++m) {
+                T.dz[m] = ts[m].p.z;
+                if (ts[m].p.ph & 1) fail("diagonal term with imaginary phase");
+                double sgn = (ts[m].p.ph & 2) ? -1.0 : 1.0;
+                for (int r = 0; r < n_real; ++r) T.dw[(size_t)r * ts.size() + m] = J[(size_t)r * NQ + ts[m].n] * 0.25 * sgn;
+            }
+        } else {
+            fail("flip mask of odd or large weight");
+        }
+        T.masks.push_back(rec);
+    }
+}
+
+std::vector<Group> make_groups(const std::vector<MaskRec>& masks, int tile_bits)
+{
+    std::vector<Group> g;
+    for (uint32_t i = 0; i < (uint32_t)masks.size(); ++i) {
+        uint32_t xh = masks[i].x >> tile_bits;
+        if (g.empty() || g.back().x_high != xh) g.push_back({xh, i, 0, 0});
+        ++g.back().count;
+    }
+    return g;
+}
+
+}  // namespace syk

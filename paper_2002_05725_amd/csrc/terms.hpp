@@ -1,0 +1,86 @@
+// Host-side term builder: couplings -> Pauli strings -> flip-mask groups.
+#pragma once
+
+#include <complex>
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "common.hpp"
+
+namespace syk {
+
+// Kinds of flip mask x (the set of qubits a term flips).
+enum MaskType : uint32_t { MASK_DIAG = 0, MASK_PAIR = 2, MASK_QUAD = 4 };
+
+// One flip mask, as read by the apply kernel.  For every row r the mask adds
+// D_x(r) psi[r ^ x] to (H psi)[r], with
+//   QUAD: D_x(r) = (-1)^{popcount(r & zbase)} T[bits of r at q0..q3]
+//   PAIR: D_x(r) = (-1)^{popcount(r & zbase)} sum_e Phi[bits of r at q0,q1][e] L_e(r),
+//         L_e(r) = W_e + sum_c w_{e,c} r_c          (real, c over all qubits)
+//   DIAG: D_0(r) = sum_n d_n (-1)^{popcount(r & dz_n)}
+struct alignas(16) MaskRec {
+    uint32_t x;        // qubits flipped
+    uint32_t zbase;    // Z string shared by all terms of the mask
+    uint8_t q[4];      // flipped qubits, ascending (QUAD: 4, PAIR: 2)
+    uint32_t type_tab; // type << 28 | index into the type's tables
+};
+static_assert(sizeof(MaskRec) == 16, "MaskRec layout");
+
+// Masks with the same x >> tile_bits read the same source tile of psi.
+struct alignas(16) Group {
+    uint32_t x_high;   // (x >> tile_bits): source tile = tile ^ x_high
+    uint32_t first;    // first mask (index into the sorted mask array)
+    uint32_t count;
+    uint32_t pad;
+};
+
+// Pauli string X^x Z^z times the phase i^ph (acts as |s> -> i^ph (-1)^{|s&z|} |s^x>).
+struct Pauli {
+    uint32_t x, z;
+    int ph;
+};
+
+// chi_a without its 2^{-1/2}: X_k Z_{<k} for even a, i X_k Z_{<=k} for odd a (Y = iXZ).
+inline Pauli majorana_pauli(int a)
+{
+    int k = a >> 1;
+    uint32_t below = (1u << k) - 1u;
+    if (a & 1) return {1u << k, below | (1u << k), 1};
+    return {1u << k, below, 0};
+}
+
+// (X^x1 Z^z1)(X^x2 Z^z2) = (-1)^{|z1 & x2|} X^{x1^x2} Z^{z1^z2}
+inline Pauli pauli_mul(const Pauli& A, const Pauli& B)
+{
+    int sign = __builtin_popcount(A.z & B.x) & 1;
+    return {A.x ^ B.x, A.z ^ B.z, (A.ph + B.ph + 2 * sign) & 3};
+}
+
+// Host copy of every table, in both precisions, plus device mirrors.
+struct TermTables {
+    int N = 0, M = 0, n_real = 0;
+    int64_t n_terms = 0;
+    std::vector<MaskRec> masks;          // sorted by x
+    int n_quad = 0, n_pair = 0, n_diag = 0;
+    // QUAD tables: [n_quad][n_real][16]
+    std::vector<c128> tab4;
+    // PAIR tables: Phi [n_pair][16] (index bits*4 + e), weights [n_pair][n_real][4][M+1]
+    // (entry M holds W_e, entry c holds w_{e,c})
+    std::vector<c128> phi2;
+    std::vector<double> w2;
+    // DIAG terms: dz [n_diag], d [n_real][n_diag]
+    std::vector<uint32_t> dz;
+    std::vector<double> dw;
+};
+
+void build_tables(int N, int n_real, const double* J, TermTables& out);
+
+// Device-resident copies of the tables.
+struct DeviceTerms {
+    DevBuf masks, tab4_d, tab4_f, phi2_d, phi2_f, w2_d, w2_f, dz, dw_d, dw_f;
+};
+
+std::vector<Group> make_groups(const std::vector<MaskRec>& masks, int tile_bits);
+
+}  // namespace syk
