@@ -1,0 +1,223 @@
+"""Benchmark of the SYK hot path on one MI355X.
+
+Workload (default): N = 52 Majoranas (dim 2^26, 270,725 couplings, 15,276
+flip masks), couplings seed 0, typical state seed 1.  One step = one Lanczos
+time step of the OTOC propagation (m = 12 applications of H, two-pass
+Gram-Schmidt with FP64 inner products, FP64 tridiagonal exponential, basis
+combination) of one complex128 state by dt = 0.25.
+
+Printed: one JSON line with the OTOC time-steps/s (value), the apply_H
+roofline figure (algorithmic bytes of one apply over its HIP-event-timed
+duration, against 8 TB/s), the complex64 leg, and the CPU checker timed on a
+bounded sample of rows of the same apply.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "apply_H GB/s (% HBM peak) and OTOC time-steps/s at N=52; grad/fwd cost ratio"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_2002_05725_amd", "csrc", "apply_h.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profile(workload_key: str):
+    """HBM bytes per apply from a committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "apply_h_traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    e = d.get(workload_key)
+    if not e or e.get("kernel_sha") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_apply")
+
+
+def run_steps(api, T, psi, n, m, dt):
+    for _ in range(n):
+        api.krylov_expmv(T, psi, -1j, dt, m=m, dt=dt)
+
+
+def timed_leg(api, torch, T, psi, steps, warmup, m, dt):
+    run_steps(api, T, psi, warmup, m, dt)
+    torch.cuda.synchronize()
+    api.timing_reset()
+    api.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_steps(api, T, psi, steps, m, dt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    api.timing_enable(False)
+    n_apply, apply_ms = api.timing_read()
+    api.timing_reset()
+    return t1 - t0, n_apply, apply_ms
+
+
+def cpu_baseline(N, J, psi_host, m, target_s):
+    """The CPU checker's term-by-term apply on a contiguous block of rows,
+    scaled to one full apply, times m applications per time step."""
+    from oracle import native
+    D = psi_host.size
+    t0 = time.perf_counter()
+    native.apply_range(N, J, psi_host, 0, 256)          # calibration
+    rate = 256 / max(time.perf_counter() - t0, 1e-6)
+    rows = int(min(D, max(256, rate * target_s)))
+    t0 = time.perf_counter()
+    native.apply_range(N, J, psi_host, 0, rows)
+    t = time.perf_counter() - t0
+    t_apply = t / rows * D
+    return {
+        "value": 1.0 / (m * t_apply),
+        "unit": "time-steps/s",
+        "cores": native.num_threads(),
+        "kind": "oracle",
+        "sample": (f"term-by-term H|psi> on rows [0, {rows}) of the N={N} apply ({t:.1f} s), "
+                   f"scaled by dim/rows to {t_apply:.1f} s per apply, times m={m} applies per step; "
+                   "Gram-Schmidt and combination not counted"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--N", type=int, default=52)
+    ap.add_argument("--m", type=int, default=12)
+    ap.add_argument("--dt", type=float, default=0.25)
+    ap.add_argument("--c64-steps", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-apply", type=int, default=0,
+                    help="only run this many complex128 apply_H calls and one 1 GiB device copy "
+                         "(for hardware-counter runs), then exit")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the sharded design is described, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2002_05725_amd import api, inputs
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    dev = torch.device("cuda:0")
+    N, m, dt = args.N, args.m, args.dt
+    log(f"[bench] N={N}: drawing couplings and state")
+    J = inputs.couplings(N, 0)
+    psi_host = inputs.typical_state(N, 1)
+    D = psi_host.size
+    T = api.Terms(N, J)
+    log(f"[bench] dim={D} terms={T.n_terms} masks={T.n_masks}")
+
+    psi = torch.from_numpy(psi_host).to(dev)
+    if args.profile_apply > 0:
+        out = torch.empty_like(psi)
+        for k in range(args.profile_apply):
+            api.apply_H(T, psi, out)
+            torch.cuda.synchronize()
+            log(f"[bench] apply {k + 1}/{args.profile_apply} done")
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_apply": args.profile_apply, "N": N, "copy_bytes": 1 << 30}), flush=True)
+        return
+    log(f"[bench] complex128: {args.warmup} warmup + {args.steps} timed steps (m={m}, dt={dt})")
+    wall, n_apply, apply_ms = timed_leg(api, torch, T, psi, args.steps, args.warmup, m, dt)
+    norm = float(torch.linalg.vector_norm(psi))
+    if not math.isfinite(norm) or abs(norm - 1) > 1e-9:
+        raise SystemExit(f"unitarity check failed: |psi| = {norm}")
+    ms_step = wall / args.steps * 1e3
+    avg_apply_s = apply_ms / n_apply / 1e3
+    alg_bytes = (T.n_masks + 1) * D * 16
+    achieved = alg_bytes / avg_apply_s / 1e9
+    log(f"[bench] c128: {ms_step:.0f} ms/step, apply {avg_apply_s * 1e3:.1f} ms ({achieved:.0f} GB/s alg)")
+
+    c64 = None
+    if args.c64_steps > 0:
+        del psi
+        torch.cuda.empty_cache()
+        p64 = torch.from_numpy(psi_host).to(dev).to(torch.complex64)
+        log(f"[bench] complex64: 1 warmup + {args.c64_steps} timed steps")
+        w64, n64, ms64 = timed_leg(api, torch, T, p64, args.c64_steps, 1, m, dt)
+        a64 = ms64 / n64 / 1e3
+        c64 = {
+            "otoc_time_steps_per_s": args.c64_steps / w64,
+            "ms_per_step": w64 / args.c64_steps * 1e3,
+            "apply_ms": a64 * 1e3,
+            "apply_alg_GBps": (T.n_masks + 1) * D * 8 / a64 / 1e9,
+        }
+        c64["apply_pct_hbm_peak"] = 100 * c64["apply_alg_GBps"] / HBM_PEAK_GBS
+        del p64
+        log(f"[bench] c64: {c64['ms_per_step']:.0f} ms/step, apply {a64 * 1e3:.1f} ms")
+
+    traffic = traffic_from_profile(f"N{N}_c128")
+    out = {
+        "metric": METRIC,
+        "value": args.steps / wall,
+        "unit": "time-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {
+            "workload": f"OTOC Lanczos time step at N={N} (dim 2^{N // 2}, {T.n_terms} couplings), "
+                        f"m={m}, dt={dt}, complex128 state, FP64 inner products",
+            "N": N, "dim": D, "n_terms": T.n_terms, "n_masks": T.n_masks, "m": m, "dt": dt,
+            "couplings_seed": 0, "state_seed": 1,
+        },
+        "apply_H": {
+            "GBps_alg": achieved,
+            "pct_hbm_peak": 100 * achieved / HBM_PEAK_GBS,
+            "ms": avg_apply_s * 1e3,
+            "launches_timed": n_apply,
+            "bytes_model": "(n_masks + 1) * dim * 16 B",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+        },
+        "complex64": c64,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] CPU checker baseline")
+        out["cpu_baseline"] = cpu_baseline(N, J, psi_host, m, args.cpu_seconds)
+    T.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

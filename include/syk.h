@@ -89,6 +89,22 @@ syk_status syk_terms_info(syk_terms t, int* N, int* n_real, int64_t* dim, int64_
 syk_status syk_apply_H(syk_terms t, syk_dtype dtype, int nvec, const int32_t* real_of_col,
                        const void* psi, void* out, hipStream_t stream);
 
+/* Launch shape of apply_H for this handle (used by the autotuner): each
+ * workgroup owns 2^tile_bits rows (0 = automatic), with `threads` threads
+ * (0 = automatic, else 64, 128 or 256); xcd_remap = 1 hands each of the 8 XCDs
+ * a contiguous range of row tiles, 0 keeps the hardware's round-robin order.
+ * Shapes that cannot launch give SYK_EINVAL and leave the setting unchanged. */
+syk_status syk_set_apply_tuning(syk_terms t, int tile_bits, int threads, int xcd_remap);
+
+/* Kernel timing: while enabled, every apply_H call records a HIP event before
+ * and after its kernel launches on the call's stream.  syk_timing_read waits
+ * for the recorded events and returns the number of timed apply_H calls and
+ * their summed duration in milliseconds; syk_timing_reset discards them.
+ * Process-wide; off by default. */
+syk_status syk_timing_enable(int on);
+syk_status syk_timing_read(int64_t* launches, double* total_ms);
+syk_status syk_timing_reset(void);
+
 /* out = chi_a psi for one Majorana 0 <= a < N (SI Jordan-Wigner map), every
  * column.  out must not overlap psi. */
 syk_status syk_apply_majorana(syk_terms t, syk_dtype dtype, int a, int nvec, const void* psi,

@@ -42,6 +42,10 @@ _SIGS = {
     "syk_terms_info": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i64),
                             ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "syk_apply_H": (_i, [_vp, _i, _i, _vp, _vp, _vp, _vp]),
+    "syk_set_apply_tuning": (_i, [_vp, _i, _i, _i]),
+    "syk_timing_enable": (_i, [_i]),
+    "syk_timing_read": (_i, [ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
+    "syk_timing_reset": (_i, []),
     "syk_apply_majorana": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
     "syk_dot": (_i, [_i, _i64, _i, _vp, _vp, _vp, _vp]),
     "syk_krylov_expmv": (_i, [_vp, _i, _i, _vp, _d, _d, _d, ctypes.POINTER(KrylovOpts), _vp, _vp, _vp]),

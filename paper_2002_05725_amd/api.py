@@ -95,6 +95,27 @@ class Terms:
             pass
 
 
+def set_apply_tuning(terms: Terms, tile_bits: int = 0, threads: int = 0, xcd_remap: int = 1):
+    """Launch shape of apply_H for this handle (0 = automatic); see syk_set_apply_tuning."""
+    check(lib().syk_set_apply_tuning(terms.handle, int(tile_bits), int(threads), int(xcd_remap)),
+          "syk_set_apply_tuning")
+
+
+def timing_enable(on: bool = True):
+    check(lib().syk_timing_enable(1 if on else 0), "syk_timing_enable")
+
+
+def timing_reset():
+    check(lib().syk_timing_reset(), "syk_timing_reset")
+
+
+def timing_read():
+    """(number of timed apply_H calls, summed milliseconds) since the last reset."""
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    check(lib().syk_timing_read(ctypes.byref(n), ctypes.byref(ms)), "syk_timing_read")
+    return n.value, ms.value
+
+
 def build_terms(N: int, J) -> Terms:
     return Terms(N, J)
 

@@ -4,6 +4,7 @@
 #include <string>
 
 #include "estimators.hpp"
+#include "timing.hpp"
 
 using namespace syk;
 
@@ -190,9 +191,50 @@ syk_status syk_apply_H(syk_terms t, syk_dtype dtype, int nvec, const int32_t* re
         check_ptr(out, "out");
         const size_t bytes = ((size_t)1 << t->H.M) * nvec * elem_bytes(dtype);
         check_no_overlap(psi, out, bytes);
-        ApplyPlan P = plan_apply(t->H.M, nvec, dtype, nullptr);
+        ApplyPlan P = plan_for(*t, nvec, dtype);
         launch_apply_h(t->H, dtype, nvec, real_of_col, psi, out, P, stream);
     });
+}
+
+syk_status syk_set_apply_tuning(syk_terms t, int tile_bits, int threads, int xcd_remap)
+{
+    return guard([&] {
+        check_handle(t);
+        require(tile_bits >= 0 && tile_bits <= 30, "tile_bits must be in [0, 30]");
+        require(threads == 0 || threads == 64 || threads == 128 || threads == 256, "threads must be 0, 64, 128 or 256");
+        require(xcd_remap == 0 || xcd_remap == 1, "xcd_remap must be 0 or 1");
+        const bool o_tuned = t->tuned;
+        const int o_tb = t->tune_tile_bits, o_nt = t->tune_threads, o_x = t->tune_xcd;
+        t->tuned = true;
+        t->tune_tile_bits = tile_bits;
+        t->tune_threads = threads;
+        t->tune_xcd = xcd_remap;
+        try {
+            (void)plan_for(*t, 1, SYK_C128);   // reject shapes that cannot launch
+            (void)plan_for(*t, 1, SYK_C64);
+        } catch (...) {
+            t->tuned = o_tuned;
+            t->tune_tile_bits = o_tb;
+            t->tune_threads = o_nt;
+            t->tune_xcd = o_x;
+            throw;
+        }
+    });
+}
+
+syk_status syk_timing_enable(int on)
+{
+    return guard([&] { timing_enable(on != 0); });
+}
+
+syk_status syk_timing_read(int64_t* launches, double* total_ms)
+{
+    return guard([&] { timing_read(launches, total_ms); });
+}
+
+syk_status syk_timing_reset(void)
+{
+    return guard([&] { timing_reset(); });
 }
 
 syk_status syk_apply_majorana(syk_terms t, syk_dtype dtype, int a, int nvec, const void* psi, void* out,

@@ -52,4 +52,6 @@ struct syk_terms_s {
     syk::HamiltonianDev H;
     syk::Workspace ws;
     unsigned upload_slot = 0;       // ring position of small coefficient uploads
+    bool tuned = false;             // apply_H launch shape set by syk_set_apply_tuning
+    int tune_tile_bits = 0, tune_threads = 0, tune_xcd = 1;
 };

@@ -12,7 +12,7 @@ namespace syk {
 
 BlockCtx::BlockCtx(syk_terms_s& h_, syk_dtype dt, int nvec_, const int32_t* real, hipStream_t s)
     : h(h_), dtype(dt), nvec(nvec_), real_of_col(real), stream(s),
-      plan(plan_apply(h_.H.M, nvec_, dt, nullptr)), ops(h_, dt, (int64_t)1 << h_.H.M, nvec_, s)
+      plan(plan_for(h_, nvec_, dt)), ops(h_, dt, (int64_t)1 << h_.H.M, nvec_, s)
 {
 }
 

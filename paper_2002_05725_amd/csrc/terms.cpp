@@ -163,10 +163,27 @@ std::vector<Group> make_groups(const std::vector<MaskRec>& masks, int tile_bits)
 {
     std::vector<Group> g;
     for (uint32_t i = 0; i < (uint32_t)masks.size(); ++i) {
-        uint32_t xh = masks[i].x >> tile_bits;
-        if (g.empty() || g.back().x_high != xh) g.push_back({xh, i, 0, 0});
-        ++g.back().count;
+        const uint32_t xh = masks[i].x >> tile_bits;
+        const bool same = !g.empty() && g.back().x_high == xh;
+        if (!same || g.back().count == (uint32_t)kChunkMasks) {
+            Group c{};
+            c.x_high = xh;
+            c.first = i;
+            c.new_tile = same ? 0u : 1u;
+            c.quad_first = 0xffffffffu;
+            g.push_back(c);
+        }
+        Group& c = g.back();
+        ++c.count;
+        if ((masks[i].type_tab >> 28) == MASK_QUAD) {
+            const uint32_t tab = masks[i].type_tab & 0x0fffffffu;
+            if (c.n_quad == 0) c.quad_first = tab;
+            if (tab != c.quad_first + c.n_quad) throw Error(SYK_EUNSUPPORTED, "QUAD tables not consecutive");
+            ++c.n_quad;
+        }
     }
+    for (Group& c : g)
+        if (c.n_quad == 0) c.quad_first = 0;
     return g;
 }
 

@@ -27,12 +27,18 @@ struct alignas(16) MaskRec {
 };
 static_assert(sizeof(MaskRec) == 16, "MaskRec layout");
 
-// Masks with the same x >> tile_bits read the same source tile of psi.
+// Masks with the same x >> tile_bits read the same source tile of psi.  The
+// run of such masks is cut into chunks of at most kChunkMasks masks whose
+// QUAD tables fit in LDS next to the source tile.
+constexpr int kChunkMasks = 64;
 struct alignas(16) Group {
-    uint32_t x_high;   // (x >> tile_bits): source tile = tile ^ x_high
-    uint32_t first;    // first mask (index into the sorted mask array)
+    uint32_t x_high;      // (x >> tile_bits): source tile = tile ^ x_high
+    uint32_t first;       // first mask (index into the sorted mask array)
     uint32_t count;
-    uint32_t pad;
+    uint32_t quad_first;  // QUAD table index of the chunk's first QUAD mask
+    uint32_t n_quad;      // QUAD masks in the chunk (their tables are consecutive)
+    uint32_t new_tile;    // x_high differs from the previous chunk's
+    uint32_t pad[2];
 };
 
 // Pauli string X^x Z^z times the phase i^ph (acts as |s> -> i^ph (-1)^{|s&z|} |s^x>).
