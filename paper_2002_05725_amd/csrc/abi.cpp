@@ -136,6 +136,7 @@ syk_status syk_build_terms(int N, int n_real, const double* J, syk_terms* out)
         upload(d.masks, T.masks);
         upload(d.tab4_d, T.tab4);
         upload(d.tab4_f, to_c64(T.tab4));
+        upload(d.qinfo, T.qinfo);
         upload(d.phi2_d, T.phi2);
         upload(d.phi2_f, to_c64(T.phi2));
         upload(d.w2_d, T.w2);
@@ -151,6 +152,7 @@ syk_status syk_build_terms(int N, int n_real, const double* J, syk_terms* out)
         H.masks = d.masks.as<MaskRec>();
         H.tab4_d = d.tab4_d.as<c128>();
         H.tab4_f = d.tab4_f.as<c64>();
+        H.qinfo = d.qinfo.as<uint32_t>();
         H.phi2_d = d.phi2_d.as<c128>();
         H.phi2_f = d.phi2_f.as<c64>();
         H.w2_d = d.w2_d.as<double>();
@@ -159,6 +161,7 @@ syk_status syk_build_terms(int N, int n_real, const double* J, syk_terms* out)
         H.dw_d = d.dw_d.as<double>();
         H.dw_f = d.dw_f.as<float>();
         H.host_masks = &T.masks;
+        H.bin_off = &T.bin_off;
         *out = h.release();
     });
 }

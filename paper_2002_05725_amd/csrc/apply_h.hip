@@ -26,6 +26,7 @@ struct KTerms {
     const MaskRec* __restrict__ masks;
     const Group* __restrict__ groups;
     const cplx<R>* __restrict__ tab4;
+    const uint32_t* __restrict__ qinfo;
     const cplx<R>* __restrict__ phi2;
     const R* __restrict__ w2;
     const uint32_t* __restrict__ dz;
@@ -63,25 +64,53 @@ __device__ __forceinline__ float flip(float x, uint32_t s) { return __int_as_flo
 
 __device__ __forceinline__ uint32_t bit(uint32_t r, uint32_t q) { return (r >> q) & 1u; }
 
-template <typename R, int RPT>
-__global__ void __launch_bounds__(256) k_apply_single(KTerms<R> T, KLayout L, const cplx<R>* __restrict__ psi,
-                                                       cplx<R>* __restrict__ out)
+// 4-bit QUAD table index: bit m = bit q_m of r.
+__device__ __forceinline__ uint32_t quad_index(uint32_t r, uint32_t qpack)
 {
+    return bit(r, mask_q(qpack, 0)) | (bit(r, mask_q(qpack, 1)) << 1) | (bit(r, mask_q(qpack, 2)) << 2) |
+           (bit(r, mask_q(qpack, 3)) << 3);
+}
+
+}  // namespace
+
+namespace {
+
+// Thread layout of the single-vector kernel: row rl = tid + k * nt of the tile
+// (nt = 2^lane_bits threads, k < RPT).  A row index splits into lane bits
+// (tid, per lane), row bits (k, the same for every lane) and tile bits (base,
+// the same for the workgroup).  The tile bits of every QUAD table index and
+// sign are folded into the tables while they are staged; the row bits come
+// from the mask record; only the lane bits are computed per thread, once per
+// mask.
+template <typename R, int RPT>
+__global__ void __launch_bounds__(256) k_apply_single(KTerms<R> T, const KRec* __restrict__ krec, KLayout L,
+                                                       const cplx<R>* __restrict__ psi, cplx<R>* __restrict__ out)
+{
+    static_assert(RPT <= 12, "row info holds 12 rows");
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int nt = blockDim.x;
-    const int tile_elems = nt * RPT;                   // == 2^tile_bits
+    const uint32_t nt = blockDim.x;
+    const uint32_t tile_elems = nt * RPT;               // == 2^tile_bits
     cplx<R>* src = reinterpret_cast<cplx<R>*>(smem_raw);
-    cplx<R>* tabs = src + tile_elems;                  // kChunkMasks x 16 entries
+    cplx<R>* tabs = src + tile_elems;                   // kChunkMasks x 16 entries
 
     const uint32_t tile = tile_of_block(blockIdx.x, L);
     const uint32_t row_mask = (1u << L.tile_bits) - 1u;
+    const uint32_t kmask = row_mask & ~(nt - 1u);       // row bits that vary with k
+    const uint32_t tid = threadIdx.x;
     const int rc = L.real[0];
     const int M = T.M;
     const uint32_t base = tile << L.tile_bits;
 
+    // complex128 sums directly in pr/pi; complex64 sums each chunk in FP32 and
+    // carries the running total in FP64.
+    constexpr bool kSplit = sizeof(R) < sizeof(double);
     double acc_re[RPT], acc_im[RPT];
+    R pr[RPT], pi[RPT];
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) acc_re[k] = acc_im[k] = 0.0;
+    for (int k = 0; k < RPT; ++k) {
+        acc_re[k] = acc_im[k] = 0.0;
+        pr[k] = pi[k] = R(0);
+    }
 
     for (int g = 0; g < T.n_groups; ++g) {
         const Group G = T.groups[g];
@@ -89,66 +118,95 @@ __global__ void __launch_bounds__(256) k_apply_single(KTerms<R> T, KLayout L, co
         if (G.new_tile) {
             const uint64_t sbase = (uint64_t)(tile ^ G.x_high) << L.tile_bits;
 #pragma unroll
-            for (int k = 0; k < RPT; ++k) src[threadIdx.x + k * nt] = psi[sbase + threadIdx.x + k * nt];
+            for (int k = 0; k < RPT; ++k) src[tid + k * nt] = psi[sbase + tid + k * nt];
         }
-        for (int e = threadIdx.x; e < (int)G.n_quad * 16; e += nt)
-            tabs[e] = T.tab4[((size_t)(G.quad_first + (e >> 4)) * T.n_real + rc) * 16 + (e & 15)];
+        // Staged QUAD table entry i of mask j: sign_tile * T[i ^ index_tile].
+        for (uint32_t e = tid; e < G.n_quad * 16; e += nt) {
+            const uint32_t qt = G.quad_first + (e >> 4);
+            const uint32_t qp = T.qinfo[2 * qt], zb = T.qinfo[2 * qt + 1];
+            const cplx<R> c = T.tab4[((size_t)qt * T.n_real + rc) * 16 + ((e & 15u) ^ quad_index(base, qp))];
+            const uint32_t sg = parity(base & zb);
+            cplx<R> o;
+            o.re = flip(c.re, sg);
+            o.im = flip(c.im, sg);
+            tabs[e] = o;
+        }
         __syncthreads();
 
-        R pr[RPT], pi[RPT];
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) pr[k] = pi[k] = R(0);
-
         for (uint32_t mi = G.first; mi < G.first + G.count; ++mi) {
-            const MaskRec m = T.masks[mi];
-            const uint32_t xl = m.x & row_mask;
-            const uint32_t type = m.type_tab >> 28;
-            const uint32_t tab = m.type_tab & 0x0fffffffu;
+            const KRec m = krec[mi];
+            const uint32_t type = m.meta >> 28;
+            const uint32_t tab = m.meta & 0x03ffffffu;
             if (type == MASK_QUAD) {
+                const uint32_t path = (m.meta >> 26) & 3u;
                 const cplx<R>* tq = tabs + (tab - G.quad_first) * 16;
-                const uint32_t q0 = m.q[0], q1 = m.q[1], q2 = m.q[2], q3 = m.q[3];
+                const uint32_t il = quad_index(tid, m.qpack);   // lane bits of the index
+                const uint32_t sl = parity(tid & m.zbase);      // lane bits of the sign
+                if (path != PATH_FULL) {
+                    const cplx<R> t = tq[il];
+                    const R tr = flip(t.re, sl), ti = flip(t.im, sl);
 #pragma unroll
-                for (int k = 0; k < RPT; ++k) {
-                    const uint32_t rl = threadIdx.x + k * nt;
-                    const uint32_t r = base | rl;
-                    const cplx<R> v = src[rl ^ xl];
-                    const uint32_t idx = bit(r, q0) | (bit(r, q1) << 1) | (bit(r, q2) << 2) | (bit(r, q3) << 3);
-                    const cplx<R> t = tq[idx];
-                    const uint32_t s = parity(r & m.zbase);
-                    const R tr = flip(t.re, s), ti = flip(t.im, s);
-                    pr[k] = fma(tr, v.re, pr[k]);
-                    pr[k] = fma(-ti, v.im, pr[k]);
-                    pi[k] = fma(tr, v.im, pi[k]);
-                    pi[k] = fma(ti, v.re, pi[k]);
+                    for (int k = 0; k < RPT; ++k) {
+                        const uint32_t sk = (path == PATH_SIGN) ? (m.kinfo[k / 6] >> (5 * (k % 6) + 4)) & 1u : 0u;
+                        const R a = flip(tr, sk), b = flip(ti, sk);
+                        const cplx<R> v = src[(tid + k * nt) ^ m.xl];
+                        pr[k] = fma(a, v.re, pr[k]);
+                        pr[k] = fma(-b, v.im, pr[k]);
+                        pi[k] = fma(a, v.im, pi[k]);
+                        pi[k] = fma(b, v.re, pi[k]);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) {
+                        const uint32_t ki = (m.kinfo[k / 6] >> (5 * (k % 6))) & 31u;
+                        const cplx<R> t = tq[il | (ki & 15u)];
+                        const uint32_t s = sl ^ (ki >> 4);
+                        const R a = flip(t.re, s), b = flip(t.im, s);
+                        const cplx<R> v = src[(tid + k * nt) ^ m.xl];
+                        pr[k] = fma(a, v.re, pr[k]);
+                        pr[k] = fma(-b, v.im, pr[k]);
+                        pi[k] = fma(a, v.im, pi[k]);
+                        pi[k] = fma(b, v.re, pi[k]);
+                    }
                 }
             } else if (type == MASK_PAIR) {
                 // D = (-1)^{|r & zbase|} sum_e phi_e (-1)^{s_q0 e_0 + s_q1 e_1} L_e(r),
-                // phi_e = Phi[idx = 3][e] (the entry with s_q0 = s_q1 = 0).
+                // phi_e = Phi[idx = 3][e] (the entry with s_q0 = s_q1 = 0),
+                // L_e(r) = W_e + sum_c w_{e,c} r_c split into lane/tile bits (once)
+                // and row bits (per k).
                 const R* w = T.w2 + ((size_t)tab * T.n_real + rc) * 4 * (M + 1);
                 const cplx<R>* ph = T.phi2 + (size_t)tab * 16 + 12;
-                const uint32_t q0 = m.q[0], q1 = m.q[1];
+                R l0 = w[M], l1 = w[(M + 1) + M], l2 = w[2 * (M + 1) + M], l3 = w[3 * (M + 1) + M];
+                for (int c = 0; c < M; ++c) {
+                    if ((1u << c) & kmask) continue;
+                    const R b = (R)bit(tid | base, c);
+                    l0 = fma(w[c], b, l0);
+                    l1 = fma(w[(M + 1) + c], b, l1);
+                    l2 = fma(w[2 * (M + 1) + c], b, l2);
+                    l3 = fma(w[3 * (M + 1) + c], b, l3);
+                }
+                const uint32_t sl = parity(tid & m.zbase);
+                const uint32_t q0 = mask_q(m.qpack, 0), q1 = mask_q(m.qpack, 1);
 #pragma unroll
                 for (int k = 0; k < RPT; ++k) {
-                    const uint32_t rl = threadIdx.x + k * nt;
-                    const uint32_t r = base | rl;
-                    const cplx<R> v = src[rl ^ xl];
-                    R l0 = w[M], l1 = w[(M + 1) + M], l2 = w[2 * (M + 1) + M], l3 = w[3 * (M + 1) + M];
-                    for (int c = 0; c < M; ++c) {
-                        const R b = (R)bit(r, c);
-                        l0 = fma(w[c], b, l0);
-                        l1 = fma(w[(M + 1) + c], b, l1);
-                        l2 = fma(w[2 * (M + 1) + c], b, l2);
-                        l3 = fma(w[3 * (M + 1) + c], b, l3);
+                    const uint32_t ru = base | (k * nt);
+                    R k0 = l0, k1 = l1, k2 = l2, k3 = l3;
+                    for (uint32_t rb = ru & kmask; rb; rb &= rb - 1) {
+                        const int c = __ffs(rb) - 1;
+                        k0 += w[c];
+                        k1 += w[(M + 1) + c];
+                        k2 += w[2 * (M + 1) + c];
+                        k3 += w[3 * (M + 1) + c];
                     }
+                    const uint32_t r = tid | ru;
                     const uint32_t sa = bit(r, q0) ^ 1u, sb = bit(r, q1) ^ 1u;
-                    l1 = flip(l1, sa);
-                    l2 = flip(l2, sb);
-                    l3 = flip(l3, sa ^ sb);
-                    R dre = ph[0].re * l0 + ph[1].re * l1 + ph[2].re * l2 + ph[3].re * l3;
-                    R dim = ph[0].im * l0 + ph[1].im * l1 + ph[2].im * l2 + ph[3].im * l3;
-                    const uint32_t s = parity(r & m.zbase);
-                    dre = flip(dre, s);
-                    dim = flip(dim, s);
+                    k1 = flip(k1, sa);
+                    k2 = flip(k2, sb);
+                    k3 = flip(k3, sa ^ sb);
+                    const uint32_t s = sl ^ parity(ru & m.zbase);
+                    const R dre = flip(ph[0].re * k0 + ph[1].re * k1 + ph[2].re * k2 + ph[3].re * k3, s);
+                    const R dim = flip(ph[0].im * k0 + ph[1].im * k1 + ph[2].im * k2 + ph[3].im * k3, s);
+                    const cplx<R> v = src[(tid + k * nt) ^ m.xl];
                     pr[k] = fma(dre, v.re, pr[k]);
                     pr[k] = fma(-dim, v.im, pr[k]);
                     pi[k] = fma(dre, v.im, pi[k]);
@@ -158,9 +216,8 @@ __global__ void __launch_bounds__(256) k_apply_single(KTerms<R> T, KLayout L, co
                 const R* d = T.dw + (size_t)rc * T.n_diag;
 #pragma unroll
                 for (int k = 0; k < RPT; ++k) {
-                    const uint32_t rl = threadIdx.x + k * nt;
-                    const uint32_t r = base | rl;
-                    const cplx<R> v = src[rl ^ xl];
+                    const uint32_t r = base | (tid + k * nt);
+                    const cplx<R> v = src[(tid + k * nt) ^ m.xl];
                     R s = R(0);
                     for (int n = 0; n < T.n_diag; ++n) s += flip(d[n], parity(r & T.dz[n]));
                     pr[k] = fma(s, v.re, pr[k]);
@@ -168,18 +225,21 @@ __global__ void __launch_bounds__(256) k_apply_single(KTerms<R> T, KLayout L, co
                 }
             }
         }
+        if (kSplit) {
 #pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            acc_re[k] += (double)pr[k];
-            acc_im[k] += (double)pi[k];
+            for (int k = 0; k < RPT; ++k) {
+                acc_re[k] += (double)pr[k];
+                acc_im[k] += (double)pi[k];
+                pr[k] = pi[k] = R(0);
+            }
         }
     }
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         cplx<R> o;
-        o.re = (R)acc_re[k];
-        o.im = (R)acc_im[k];
-        out[(uint64_t)base + threadIdx.x + k * nt] = o;
+        o.re = kSplit ? (R)acc_re[k] : pr[k];
+        o.im = kSplit ? (R)acc_im[k] : pi[k];
+        out[(uint64_t)base + tid + k * nt] = o;
     }
 }
 
@@ -242,8 +302,7 @@ __global__ void __launch_bounds__(256) k_apply_block(KTerms<R> T, KLayout L, con
                 for (int k = 0; k < RPT; ++k) {
                     const cplx<R> v = src[lin[k] ^ xl_sh];
                     const uint32_t r = row[k];
-                    const uint32_t idx = bit(r, m.q[0]) | (bit(r, m.q[1]) << 1) | (bit(r, m.q[2]) << 2) |
-                                         (bit(r, m.q[3]) << 3);
+                    const uint32_t idx = quad_index(r, m.qpack);
                     const cplx<R> t = T.tab4[((size_t)tab * T.n_real + rc[k]) * 16 + idx];
                     const uint32_t s = parity(r & m.zbase);
                     const R tr = flip(t.re, s), ti = flip(t.im, s);
@@ -267,7 +326,7 @@ __global__ void __launch_bounds__(256) k_apply_block(KTerms<R> T, KLayout L, con
                         l2 = fma(w[2 * (M + 1) + c], b, l2);
                         l3 = fma(w[3 * (M + 1) + c], b, l3);
                     }
-                    const uint32_t sa = bit(r, m.q[0]) ^ 1u, sb = bit(r, m.q[1]) ^ 1u;
+                    const uint32_t sa = bit(r, mask_q(m.qpack, 0)) ^ 1u, sb = bit(r, mask_q(m.qpack, 1)) ^ 1u;
                     l1 = flip(l1, sa);
                     l2 = flip(l2, sb);
                     l3 = flip(l3, sa ^ sb);
@@ -317,7 +376,8 @@ inline int ilog2(int64_t v)
 }
 
 template <typename R>
-void launch_t(const ApplyPlan& P, const KTerms<R>& T, KLayout L, const void* psi, void* out, hipStream_t s)
+void launch_t(const ApplyPlan& P, const KTerms<R>& T, const KRec* krec, KLayout L, const void* psi, void* out,
+              hipStream_t s)
 {
     dim3 grid(L.n_tiles), block(P.nt);
     const size_t tile = ((size_t)1 << (P.tile_bits + P.log_cw)) * sizeof(cplx<R>);
@@ -326,11 +386,10 @@ void launch_t(const ApplyPlan& P, const KTerms<R>& T, KLayout L, const void* psi
     if (P.single) {
         const size_t lds = tile + (size_t)kChunkMasks * 16 * sizeof(cplx<R>);
         switch (P.rpt) {
-        case 1: hipLaunchKernelGGL((k_apply_single<R, 1>), grid, block, lds, s, T, L, in, o); break;
-        case 2: hipLaunchKernelGGL((k_apply_single<R, 2>), grid, block, lds, s, T, L, in, o); break;
-        case 4: hipLaunchKernelGGL((k_apply_single<R, 4>), grid, block, lds, s, T, L, in, o); break;
-        case 8: hipLaunchKernelGGL((k_apply_single<R, 8>), grid, block, lds, s, T, L, in, o); break;
-        case 16: hipLaunchKernelGGL((k_apply_single<R, 16>), grid, block, lds, s, T, L, in, o); break;
+        case 1: hipLaunchKernelGGL((k_apply_single<R, 1>), grid, block, lds, s, T, krec, L, in, o); break;
+        case 2: hipLaunchKernelGGL((k_apply_single<R, 2>), grid, block, lds, s, T, krec, L, in, o); break;
+        case 4: hipLaunchKernelGGL((k_apply_single<R, 4>), grid, block, lds, s, T, krec, L, in, o); break;
+        case 8: hipLaunchKernelGGL((k_apply_single<R, 8>), grid, block, lds, s, T, krec, L, in, o); break;
         default: throw Error(SYK_EINVAL, "apply_H: unsupported rows per thread");
         }
     } else {
@@ -346,7 +405,57 @@ void launch_t(const ApplyPlan& P, const KTerms<R>& T, KLayout L, const void* psi
     SYK_HIP(hipGetLastError());
 }
 
+// Mask records for launch shape (tile_bits, nt), in mask order.
+std::vector<KRec> build_krecs(const std::vector<MaskRec>& masks, const std::vector<uint64_t>& bin_off, int tile_bits,
+                             int nt)
+{
+    const uint32_t row_mask = (1u << tile_bits) - 1u;
+    const uint32_t kmask = row_mask & ~((uint32_t)nt - 1u);
+    const int rpt = (1 << tile_bits) / nt;
+    std::vector<KRec> out(masks.size());
+    for (size_t i = 0; i < masks.size(); ++i) {
+        const MaskRec& m = masks[i];
+        KRec k{};
+        k.xl = m.x & row_mask;
+        k.qpack = m.qpack;
+        k.zbase = m.zbase;
+        const uint32_t type = m.type_tab >> 28, tab = m.type_tab & 0x0fffffffu;
+        uint32_t path = PATH_SAME;
+        if (type == MASK_QUAD) {
+            if (m.x & kmask) path = PATH_FULL;
+            else if (m.zbase & kmask) path = PATH_SIGN;
+            for (int r = 0; r < rpt && r < 12; ++r) {
+                const uint32_t ru = (uint32_t)r * (uint32_t)nt;
+                uint32_t ik = 0;
+                for (int j = 0; j < 4; ++j) ik |= ((ru >> mask_q(m.qpack, j)) & 1u) << j;
+                const uint32_t sk = (uint32_t)__builtin_popcount(ru & m.zbase) & 1u;
+                k.kinfo[r / 6] |= (ik | sk << 4) << (5 * (r % 6));
+            }
+        }
+        if (tab >= (1u << 26)) throw Error(SYK_EUNSUPPORTED, "apply_H: too many masks");
+        k.meta = type << 28 | path << 26 | tab;
+        k.pad[0] = (uint32_t)bin_off[i];
+        out[i] = k;
+    }
+    return out;
+}
+
 }  // namespace
+
+const KRec* krecs_for(const HamiltonianDev& H, const ApplyPlan& P)
+{
+    const int key = P.tile_bits * 4096 + P.nt;
+    auto it = H.krecs.find(key);
+    if (it == H.krecs.end()) {
+        if (H.bin_off->size() != H.host_masks->size()) throw Error(SYK_EINVAL, "apply_H: handle tables incomplete");
+        std::vector<KRec> v = build_krecs(*H.host_masks, *H.bin_off, P.tile_bits, P.nt);
+        std::unique_ptr<DevBuf> b(new DevBuf());
+        b->ensure(v.size() * sizeof(KRec));
+        SYK_HIP(hipMemcpy(b->p, v.data(), v.size() * sizeof(KRec), hipMemcpyHostToDevice));
+        it = H.krecs.emplace(key, std::move(b)).first;
+    }
+    return it->second->as<KRec>();
+}
 
 ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune)
 {
@@ -357,8 +466,9 @@ ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune)
     P.log_cw = ilog2(cw);
     P.slices = nvec / cw;
     P.single = (nvec == 1);
-    // LDS source tile of 16 KiB (two or more workgroups per CU).
-    const int max_elems_log = (dtype == SYK_C128) ? 10 : 11;
+    // 1024-row source tiles (16 KiB complex128, 8 KiB complex64): measured best
+    // at N=44 and N=52 on MI355X.
+    const int max_elems_log = 10;
     int tb = std::min(M, max_elems_log - P.log_cw);
     if (tb < 0) tb = 0;
     // Keep enough workgroups to fill 256 CUs several times over.
@@ -372,11 +482,11 @@ ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune)
     if (tune && tune->threads > 0) nt_pref = tune->threads;
     P.tile_bits = tb;
     const int elems = 1 << (tb + P.log_cw);
+    const int max_rpt = P.single ? 8 : 16;
     P.nt = std::min(nt_pref, elems);
-    while (elems / P.nt > 16) P.nt *= 2;
-    if (P.nt > 256) P.nt = 256;
+    while (elems / P.nt > max_rpt && P.nt < 256) P.nt *= 2;
     P.rpt = elems / P.nt;
-    if (P.rpt > 16 || P.rpt * P.nt != elems) throw Error(SYK_EINVAL, "apply_H: tile does not fit the launch shape");
+    if (P.rpt > max_rpt || P.rpt * P.nt != elems) throw Error(SYK_EINVAL, "apply_H: tile does not fit the launch shape");
     P.xcd_remap = tune ? tune->xcd_remap : 1;
     return P;
 }
@@ -388,6 +498,7 @@ void launch_apply_h(const HamiltonianDev& H, syk_dtype dtype, int nvec, const in
     const Group* groups = H.groups_for(P.tile_bits);
     const int n_groups = H.n_groups_for(P.tile_bits);
     const int cw = 1 << P.log_cw;
+    const KRec* krec = P.single ? krecs_for(H, P) : nullptr;
     timing_begin(s);
     for (int sl = 0; sl < P.slices; ++sl) {
         KLayout L{};
@@ -399,13 +510,13 @@ void launch_apply_h(const HamiltonianDev& H, syk_dtype dtype, int nvec, const in
         L.xcd_remap = P.xcd_remap;
         for (int c = 0; c < cw; ++c) L.real[c] = real_of_col ? real_of_col[L.col0 + c] : 0;
         if (dtype == SYK_C128) {
-            KTerms<double> T{H.masks, groups, H.tab4_d, H.phi2_d, H.w2_d, H.dz, H.dw_d,
+            KTerms<double> T{H.masks, groups, H.tab4_d, H.qinfo, H.phi2_d, H.w2_d, H.dz, H.dw_d,
                              n_groups, H.n_diag, H.n_real, M};
-            launch_t<double>(P, T, L, psi, out, s);
+            launch_t<double>(P, T, krec, L, psi, out, s);
         } else {
-            KTerms<float> T{H.masks, groups, H.tab4_f, H.phi2_f, H.w2_f, H.dz, H.dw_f,
+            KTerms<float> T{H.masks, groups, H.tab4_f, H.qinfo, H.phi2_f, H.w2_f, H.dz, H.dw_f,
                             n_groups, H.n_diag, H.n_real, M};
-            launch_t<float>(P, T, L, psi, out, s);
+            launch_t<float>(P, T, krec, L, psi, out, s);
         }
     }
     timing_end(s);

@@ -15,6 +15,7 @@ struct HamiltonianDev {
     const MaskRec* masks = nullptr;
     const c128* tab4_d = nullptr;
     const c64* tab4_f = nullptr;
+    const uint32_t* qinfo = nullptr;
     const c128* phi2_d = nullptr;
     const c64* phi2_f = nullptr;
     const double* w2_d = nullptr;
@@ -24,10 +25,13 @@ struct HamiltonianDev {
     const float* dw_f = nullptr;
     // Group lists for each tile size, built on first use.
     const std::vector<MaskRec>* host_masks = nullptr;
+    const std::vector<uint64_t>* bin_off = nullptr;
     mutable std::map<int, std::unique_ptr<DevBuf>> groups;
     mutable std::map<int, int> n_groups;
     const Group* groups_for(int tile_bits) const;
     int n_groups_for(int tile_bits) const;
+    // Per-launch-shape mask records of the single-vector kernel, built on first use.
+    mutable std::map<int, std::unique_ptr<DevBuf>> krecs;
 };
 
 // Named device workspaces, grown on demand and kept until the handle dies.
@@ -52,6 +56,8 @@ struct syk_terms_s {
     syk::HamiltonianDev H;
     syk::Workspace ws;
     unsigned upload_slot = 0;       // ring position of small coefficient uploads
+    std::map<int, std::unique_ptr<syk::DevBuf>> grad_chunks;   // per tile_bits
+    std::map<int, int> grad_nchunks;
     bool tuned = false;             // apply_H launch shape set by syk_set_apply_tuning
     int tune_tile_bits = 0, tune_threads = 0, tune_xcd = 1;
 };

@@ -56,11 +56,15 @@ void build_tables(int N, int n_real, const double* J, TermTables& T)
 
     T.masks.clear();
     T.tab4.clear();
+    T.qinfo.clear();
     T.phi2.clear();
     T.w2.clear();
     T.dz.clear();
     T.dw.clear();
     T.n_quad = T.n_pair = T.n_diag = 0;
+    T.terms.assign((size_t)n, TermRef{});
+    T.bin_off.clear();
+    T.n_bins = 0;
 
     const size_t NQ = (size_t)n;
     auto coef = [&](const Term& t, int r) {   // J * i^ph / 4 for realisation r
@@ -70,11 +74,20 @@ void build_tables(int N, int n_real, const double* J, TermTables& T)
     for (uint32_t x : xs) {
         const std::vector<Term>& ts = by_x[x];
         const int w = __builtin_popcount(x);
+        const uint32_t mask_index = (uint32_t)T.masks.size();
+        for (const Term& t : ts) T.terms[t.n] = TermRef{mask_index, t.p.z, t.p.ph, -1};
+        T.bin_off.push_back(T.n_bins);
+        T.n_bins += (w == 4) ? 16 : (w == 2) ? 4 + 4 * (uint64_t)M : (uint64_t)ts.size();
         MaskRec rec{};
         rec.x = x;
         int qn = 0;
+        uint32_t q[4] = {0, 0, 0, 0};
         for (int b = 0; b < M; ++b)
-            if (x >> b & 1u) rec.q[qn++] = (uint8_t)b;
+            if (x >> b & 1u) {
+                q[qn] = (uint32_t)b;
+                rec.qpack |= (uint32_t)b << (8 * qn);
+                ++qn;
+            }
 
         if (w == 4) {
             // All 16 terms share their Z string outside the flipped qubits.
@@ -90,7 +103,7 @@ void build_tables(int N, int n_real, const double* J, TermTables& T)
                 for (int idx = 0; idx < 16; ++idx) {
                     uint32_t s_loc = 0;
                     for (int m = 0; m < 4; ++m)
-                        if (!((idx >> m) & 1)) s_loc |= 1u << rec.q[m];
+                        if (!((idx >> m) & 1)) s_loc |= 1u << q[m];
                     std::complex<double> acc = 0.0;
                     for (const Term& t : ts) {
                         double sg = (__builtin_popcount(s_loc & t.p.z) & 1) ? -1.0 : 1.0;
@@ -98,11 +111,13 @@ void build_tables(int N, int n_real, const double* J, TermTables& T)
                     }
                     T.tab4.push_back({acc.real(), acc.imag()});
                 }
+            T.qinfo.push_back(rec.qpack);
+            T.qinfo.push_back(rec.zbase);
             ++T.n_quad;
         } else if (w == 2) {
             // Terms chi_A chi_B chi_2c chi_2c+1: Z string = zbase ^ (bits at
             // q0, q1) ^ (1 << c), with c not flipped.  e = (z_q0, z_q1).
-            const uint32_t qa = rec.q[0], qb = rec.q[1];
+            const uint32_t qa = q[0], qb = q[1];
             // chi_A chi_B contributes the Z string on the qubits strictly
             // between q0 and q1 (plus bits at q0, q1); the pair adds Z_c.
             // Checked term by term below.
@@ -116,6 +131,7 @@ void build_tables(int N, int n_real, const double* J, TermTables& T)
                 uint32_t extra = (t.p.z & ~x) ^ zb;
                 if (__builtin_popcount(extra) != 1 || (extra & x)) fail("weight-2 term without a single Z_c");
                 int c = __builtin_ctz(extra);
+                T.terms[t.n].slot = c;
                 int e = (int)((t.p.z >> qa) & 1u) | (int)((t.p.z >> qb) & 1u) << 1;
                 int c_cls = t.p.ph & 1;              // 0: real phase, 1: imaginary
                 double sgn = (t.p.ph & 2) ? -1.0 : 1.0;
@@ -148,6 +164,7 @@ void build_tables(int N, int n_real, const double* J, TermTables& T)
             T.dw.assign((size_t)n_real * ts.size(), 0.0);
             for (size_t m = 0; m < ts.size(); ++m) {
                 T.dz[m] = ts[m].p.z;
+                T.terms[ts[m].n].slot = (int)m;
                 if (ts[m].p.ph & 1) fail("diagonal term with imaginary phase");
                 double sgn = (ts[m].p.ph & 2) ? -1.0 : 1.0;
                 for (int r = 0; r < n_real; ++r) T.dw[(size_t)r * ts.size() + m] = J[(size_t)r * NQ + ts[m].n] * 0.25 * sgn;
@@ -156,6 +173,43 @@ void build_tables(int N, int n_real, const double* J, TermTables& T)
             fail("flip mask of odd or large weight");
         }
         T.masks.push_back(rec);
+    }
+}
+
+void couplings_from_bins(const TermTables& T, const double* bins, double* out)
+{
+    typedef std::complex<double> C;
+    auto bin = [&](uint64_t i) { return C(bins[2 * i], bins[2 * i + 1]); };
+    const int M = T.M;
+    for (size_t n = 0; n < T.terms.size(); ++n) {
+        const TermRef& tr = T.terms[n];
+        const MaskRec& m = T.masks[tr.mask];
+        const uint64_t off = T.bin_off[tr.mask];
+        const uint32_t type = m.type_tab >> 28;
+        const C ph = iphase(tr.ph) * 0.25;
+        C s = 0.0;
+        if (type == MASK_QUAD) {
+            // the term's own 16-entry table with J = 1 (same construction as build_tables)
+            for (int idx = 0; idx < 16; ++idx) {
+                uint32_t s_loc = 0;
+                for (int j = 0; j < 4; ++j)
+                    if (!((idx >> j) & 1)) s_loc |= 1u << mask_q(m.qpack, j);
+                const double sg = (__builtin_popcount(s_loc & tr.z) & 1) ? -1.0 : 1.0;
+                s += sg * ph * bin(off + idx);
+            }
+        } else if (type == MASK_PAIR) {
+            const uint32_t qa = mask_q(m.qpack, 0), qb = mask_q(m.qpack, 1);
+            const int e0 = (int)((tr.z >> qa) & 1u), e1 = (int)((tr.z >> qb) & 1u);
+            for (int idx = 0; idx < 4; ++idx) {
+                const int sa = !(idx & 1), sb = !((idx >> 1) & 1);
+                const double sg = (((sa & e0) ^ (sb & e1)) & 1) ? -1.0 : 1.0;
+                s += sg * ph * (bin(off + idx) - 2.0 * bin(off + 4 + 4 * (uint64_t)tr.slot + idx));
+            }
+        } else {
+            s = ph * bin(off + tr.slot);
+        }
+        out[n] = s.real();
+        (void)M;
     }
 }
 

@@ -22,10 +22,12 @@ enum MaskType : uint32_t { MASK_DIAG = 0, MASK_PAIR = 2, MASK_QUAD = 4 };
 struct alignas(16) MaskRec {
     uint32_t x;        // qubits flipped
     uint32_t zbase;    // Z string shared by all terms of the mask
-    uint8_t q[4];      // flipped qubits, ascending (QUAD: 4, PAIR: 2)
+    uint32_t qpack;    // flipped qubits, ascending, one per byte (QUAD: 4, PAIR: 2)
     uint32_t type_tab; // type << 28 | index into the type's tables
 };
 static_assert(sizeof(MaskRec) == 16, "MaskRec layout");
+
+__host__ __device__ inline uint32_t mask_q(uint32_t qpack, int i) { return (qpack >> (8 * i)) & 0xffu; }
 
 // Masks with the same x >> tile_bits read the same source tile of psi.  The
 // run of such masks is cut into chunks of at most kChunkMasks masks whose
@@ -63,14 +65,23 @@ inline Pauli pauli_mul(const Pauli& A, const Pauli& B)
     return {A.x ^ B.x, A.z ^ B.z, (A.ph + B.ph + 2 * sign) & 3};
 }
 
+// Where coupling n lives in the grouped form (for derivatives in the couplings).
+struct TermRef {
+    uint32_t mask;   // index in the sorted mask array
+    uint32_t z;      // Z string of the term's Pauli string
+    int ph;          // phase exponent: the term is J * i^ph / 4 * X^x Z^z
+    int slot;        // PAIR: pair qubit c; DIAG: index in dz/dw; QUAD: unused
+};
+
 // Host copy of every table, in both precisions, plus device mirrors.
 struct TermTables {
     int N = 0, M = 0, n_real = 0;
     int64_t n_terms = 0;
     std::vector<MaskRec> masks;          // sorted by x
     int n_quad = 0, n_pair = 0, n_diag = 0;
-    // QUAD tables: [n_quad][n_real][16]
+    // QUAD tables: [n_quad][n_real][16]; qinfo [n_quad]: (qpack, zbase) of each QUAD mask
     std::vector<c128> tab4;
+    std::vector<uint32_t> qinfo;
     // PAIR tables: Phi [n_pair][16] (index bits*4 + e), weights [n_pair][n_real][4][M+1]
     // (entry M holds W_e, entry c holds w_{e,c})
     std::vector<c128> phi2;
@@ -78,13 +89,25 @@ struct TermTables {
     // DIAG terms: dz [n_diag], d [n_real][n_diag]
     std::vector<uint32_t> dz;
     std::vector<double> dw;
+    // Coupling order -> grouped form; per-mask offsets into the derivative bins
+    // (QUAD: 16 bins; PAIR: 4 + 4 M bins; DIAG: n_diag bins).
+    std::vector<TermRef> terms;
+    std::vector<uint64_t> bin_off;
+    uint64_t n_bins = 0;
 };
+
+// Derivative bins of one mask (complex, FP64), filled by the gradient kernel:
+//   QUAD  B[idx]            = sum_r conj(g[r]) (-1)^{|r & zbase|} v[r ^ x] over rows with bits idx at q0..q3
+//   PAIR  B[idx], C_c[idx]  = the same over rows with bits idx at q0, q1 (C_c: only rows with r_c = 1)
+//   DIAG  E_n               = sum_r conj(g[r]) (-1)^{|r & dz_n|} v[r]
+// d/dJ_n Re <g|H v> for every coupling n, from the bins.
+void couplings_from_bins(const TermTables& T, const double* bins /* n_bins (re, im) */, double* out);
 
 void build_tables(int N, int n_real, const double* J, TermTables& out);
 
 // Device-resident copies of the tables.
 struct DeviceTerms {
-    DevBuf masks, tab4_d, tab4_f, phi2_d, phi2_f, w2_d, w2_f, dz, dw_d, dw_f;
+    DevBuf masks, tab4_d, tab4_f, qinfo, phi2_d, phi2_f, w2_d, w2_f, dz, dw_d, dw_f;
 };
 
 std::vector<Group> make_groups(const std::vector<MaskRec>& masks, int tile_bits);
