@@ -91,7 +91,8 @@ syk_status syk_apply_H(syk_terms t, syk_dtype dtype, int nvec, const int32_t* re
 
 /* Launch shape of apply_H for this handle (used by the autotuner): each
  * workgroup owns 2^tile_bits rows (0 = automatic), with `threads` threads
- * (0 = automatic, else 64, 128 or 256); xcd_remap = 1 hands each of the 8 XCDs
+ * (0 = automatic, else a power of two in [64, 1024]; blocks of several columns
+ * use at most 256); xcd_remap = 1 hands each of the 8 XCDs
  * a contiguous range of row tiles, 0 keeps the hardware's round-robin order.
  * Shapes that cannot launch give SYK_EINVAL and leave the setting unchanged. */
 syk_status syk_set_apply_tuning(syk_terms t, int tile_bits, int threads, int xcd_remap);
@@ -169,6 +170,51 @@ syk_status syk_otoc(syk_terms t, syk_dtype dtype, int i, int j, double beta, con
                     int nt, int nvec, const int32_t* real_of_col, const void* psi0,
                     const syk_krylov_opts* opts, double* F, double* F_im, double* Z,
                     hipStream_t stream);
+
+/*
+ * Smallest and largest Ritz values of m Lanczos steps started from psi0
+ * (device, one column): inner bounds on the spectrum of realisation 0 that
+ * converge quickly at the edges.  Used to choose the Chebyshev interval; e_min
+ * also estimates the ground-state energy.
+ */
+syk_status syk_spectrum_bounds(syk_terms t, syk_dtype dtype, int m, const void* psi0, double* e_min,
+                               double* e_max, hipStream_t stream);
+
+/* Chebyshev options.  Every propagator of the OTOC becomes a fixed polynomial
+ * of this degree (2..256) in H~ = (H - e_center) / e_halfwidth: real time in
+ * steps of dt (t_star must be a multiple of dt), each imaginary-time leg in
+ * tau_steps equal steps.  The interval must enclose the spectrum and is held
+ * fixed (it does not move with J).  checkpoint_every: the reverse sweep stores
+ * one state every this many operations and recomputes the others. */
+typedef struct {
+    int degree;
+    double dt;
+    int tau_steps;
+    int checkpoint_every;
+    double e_center;
+    double e_halfwidth;
+} syk_cheb_opts;
+
+/*
+ * F(t_star) of the regularized OTOC (same estimator and symmetric cut as
+ * syk_otoc) with every propagator a Chebyshev polynomial (Jacobi-Anger
+ * expansion e^{-ihH} = sum (2-d_n0)(-i)^n J_n(e_h h) e^{-i e_c h} T_n(H~);
+ * e^{-tau H} with (-1)^n I_n(e_h tau) e^{-e_c tau}).  complex128, one column,
+ * realisation 0.  F: host scalar.
+ */
+syk_status syk_cheb_otoc(syk_terms t, int i, int j, double beta, double t_star, const syk_cheb_opts* opts,
+                         const void* psi0, double* F, hipStream_t stream);
+
+/*
+ * F(t_star) as in syk_cheb_otoc and dF/dJ_ijkl for every coupling (host, C(N,4)
+ * in lexicographic order), exact for that polynomial forward: a reverse sweep
+ * through every Chebyshev step (Clenshaw's recurrence for the adjoint states)
+ * with states recomputed from checkpoints, and per-coupling reductions
+ * Re <g| dH/dJ v> accumulated on the device.  Includes the derivative of
+ * <psi|rho|psi>.
+ */
+syk_status syk_grad_couplings(syk_terms t, int i, int j, double beta, double t_star, const syk_cheb_opts* opts,
+                              const void* psi0, double* F, double* dF_dJ, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -22,6 +22,12 @@ class KrylovOpts(ctypes.Structure):
                 ("tol", ctypes.c_double)]
 
 
+class ChebOpts(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int), ("dt", ctypes.c_double), ("tau_steps", ctypes.c_int),
+                ("checkpoint_every", ctypes.c_int), ("e_center", ctypes.c_double),
+                ("e_halfwidth", ctypes.c_double)]
+
+
 class SykError(RuntimeError):
     def __init__(self, status: int, fn: str, msg: str):
         super().__init__(f"{fn}: {STATUS_NAMES.get(status, status)}: {msg}")
@@ -52,6 +58,9 @@ _SIGS = {
     "syk_two_point": (_i, [_vp, _i, _i, _d, _vp, _i, _i, _vp, _vp, ctypes.POINTER(KrylovOpts), _vp, _vp, _vp]),
     "syk_otoc": (_i, [_vp, _i, _i, _i, _d, _vp, _i, _i, _vp, _vp, ctypes.POINTER(KrylovOpts), _vp, _vp, _vp,
                       _vp]),
+    "syk_spectrum_bounds": (_i, [_vp, _i, _i, _vp, ctypes.POINTER(_d), ctypes.POINTER(_d), _vp]),
+    "syk_cheb_otoc": (_i, [_vp, _i, _i, _d, _d, ctypes.POINTER(ChebOpts), _vp, ctypes.POINTER(_d), _vp]),
+    "syk_grad_couplings": (_i, [_vp, _i, _i, _d, _d, ctypes.POINTER(ChebOpts), _vp, ctypes.POINTER(_d), _vp, _vp]),
 }
 
 

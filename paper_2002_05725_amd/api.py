@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import KrylovOpts, check, lib
+from ._lib import ChebOpts, KrylovOpts, check, lib
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -200,3 +200,42 @@ def otoc(terms: Terms, i: int, j: int, beta: float, times, psi0: torch.Tensor, m
                          ctypes.byref(o), F.ctypes.data_as(ctypes.c_void_p), Fi.ctypes.data_as(ctypes.c_void_p),
                          Z.ctypes.data_as(ctypes.c_void_p), _stream()), "syk_otoc")
     return F, Fi, Z
+
+
+def spectrum_bounds(terms: Terms, psi0: torch.Tensor, m: int = 40):
+    """(e_min, e_max): extreme Ritz values of m Lanczos steps from psi0."""
+    _check_state(psi0, terms.dim, "psi0")
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    check(lib().syk_spectrum_bounds(terms.handle, _dtype_code(psi0), int(m), ctypes.c_void_p(psi0.data_ptr()),
+                                    ctypes.byref(lo), ctypes.byref(hi), _stream()), "syk_spectrum_bounds")
+    return lo.value, hi.value
+
+
+def cheb_opts(degree: int = 32, dt: float = 0.1, tau_steps: int = 1, checkpoint_every: int = 10,
+              e_center: float = 0.0, e_halfwidth: float = 1.0) -> ChebOpts:
+    return ChebOpts(int(degree), float(dt), int(tau_steps), int(checkpoint_every), float(e_center),
+                    float(e_halfwidth))
+
+
+def cheb_otoc(terms: Terms, i: int, j: int, beta: float, t_star: float, psi0: torch.Tensor, opts: ChebOpts) -> float:
+    """F(t_star) with Chebyshev propagators (syk_cheb_otoc); complex128 psi0 [dim]."""
+    _check_state(psi0, terms.dim, "psi0")
+    if psi0.dtype != torch.complex128 or psi0.dim() != 1:
+        raise ValueError("the Chebyshev OTOC takes one complex128 state")
+    F = ctypes.c_double()
+    check(lib().syk_cheb_otoc(terms.handle, int(i), int(j), float(beta), float(t_star), ctypes.byref(opts),
+                              ctypes.c_void_p(psi0.data_ptr()), ctypes.byref(F), _stream()), "syk_cheb_otoc")
+    return F.value
+
+
+def grad_couplings(terms: Terms, i: int, j: int, beta: float, t_star: float, psi0: torch.Tensor, opts: ChebOpts):
+    """(F, dF/dJ as a numpy array of C(N,4)) by the reverse sweep (syk_grad_couplings)."""
+    _check_state(psi0, terms.dim, "psi0")
+    if psi0.dtype != torch.complex128 or psi0.dim() != 1:
+        raise ValueError("the gradient takes one complex128 state")
+    F = ctypes.c_double()
+    g = np.empty(terms.n_terms, dtype=np.float64)
+    check(lib().syk_grad_couplings(terms.handle, int(i), int(j), float(beta), float(t_star), ctypes.byref(opts),
+                                   ctypes.c_void_p(psi0.data_ptr()), ctypes.byref(F),
+                                   g.ctypes.data_as(ctypes.c_void_p), _stream()), "syk_grad_couplings")
+    return F.value, g

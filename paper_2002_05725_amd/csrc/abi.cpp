@@ -3,6 +3,7 @@
 #include <cstring>
 #include <string>
 
+#include "cheb.hpp"
 #include "estimators.hpp"
 #include "timing.hpp"
 
@@ -204,7 +205,8 @@ syk_status syk_set_apply_tuning(syk_terms t, int tile_bits, int threads, int xcd
     return guard([&] {
         check_handle(t);
         require(tile_bits >= 0 && tile_bits <= 30, "tile_bits must be in [0, 30]");
-        require(threads == 0 || threads == 64 || threads == 128 || threads == 256, "threads must be 0, 64, 128 or 256");
+        require(threads == 0 || threads == 64 || threads == 128 || threads == 256 || threads == 512 || threads == 1024,
+                "threads must be 0 or a power of two in [64, 1024]");
         require(xcd_remap == 0 || xcd_remap == 1, "xcd_remap must be 0 or 1");
         const bool o_tuned = t->tuned;
         const int o_tb = t->tune_tile_bits, o_nt = t->tune_threads, o_x = t->tune_xcd;
@@ -337,6 +339,55 @@ syk_status syk_otoc(syk_terms t, syk_dtype dtype, int i, int j, double beta, con
         require(F != nullptr, "F is NULL");
         BlockCtx c(*t, dtype, nvec, real_of_col, stream);
         otoc(c, i, j, beta, times, nt, psi0, o, F, F_im, Z);
+    });
+}
+
+syk_status syk_spectrum_bounds(syk_terms t, syk_dtype dtype, int m, const void* psi0, double* e_min, double* e_max,
+                               hipStream_t stream)
+{
+    return guard([&] {
+        check_handle(t);
+        check_dtype(dtype);
+        require(m >= 2 && m <= 64, "m must be in [2, 64]");
+        check_ptr(psi0, "psi0");
+        require(e_min && e_max, "outputs are NULL");
+        BlockCtx c(*t, dtype, 1, nullptr, stream);
+        lanczos_extremes(c, psi0, m, e_min, e_max);
+    });
+}
+
+static ChebSettings check_cheb(syk_terms t, int i, int j, double beta, double t_star, const syk_cheb_opts* o)
+{
+    check_handle(t);
+    require(o != nullptr, "Chebyshev options are NULL");
+    require(i >= 0 && i < t->H.N && j >= 0 && j < t->H.N && i != j, "need 0 <= i, j < N with i != j");
+    require(std::isfinite(beta) && beta >= 0, "beta must be finite and >= 0");
+    require(std::isfinite(t_star) && t_star >= 0, "t_star must be finite and >= 0");
+    ChebSettings s{o->degree, o->dt, o->tau_steps, o->checkpoint_every, o->e_center, o->e_halfwidth};
+    return s;
+}
+
+syk_status syk_cheb_otoc(syk_terms t, int i, int j, double beta, double t_star, const syk_cheb_opts* opts,
+                         const void* psi0, double* F, hipStream_t stream)
+{
+    return guard([&] {
+        ChebSettings s = check_cheb(t, i, j, beta, t_star, opts);
+        check_ptr(psi0, "psi0");
+        require(F != nullptr, "F is NULL");
+        BlockCtx c(*t, SYK_C128, 1, nullptr, stream);
+        cheb_otoc(c, i, j, beta, t_star, s, psi0, F, nullptr);
+    });
+}
+
+syk_status syk_grad_couplings(syk_terms t, int i, int j, double beta, double t_star, const syk_cheb_opts* opts,
+                              const void* psi0, double* F, double* dF_dJ, hipStream_t stream)
+{
+    return guard([&] {
+        ChebSettings s = check_cheb(t, i, j, beta, t_star, opts);
+        check_ptr(psi0, "psi0");
+        require(F != nullptr && dF_dJ != nullptr, "F or dF_dJ is NULL");
+        BlockCtx c(*t, SYK_C128, 1, nullptr, stream);
+        cheb_otoc(c, i, j, beta, t_star, s, psi0, F, dF_dJ);
     });
 }
 

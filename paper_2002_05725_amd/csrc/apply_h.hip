@@ -83,7 +83,7 @@ namespace {
 // from the mask record; only the lane bits are computed per thread, once per
 // mask.
 template <typename R, int RPT>
-__global__ void __launch_bounds__(256) k_apply_single(KTerms<R> T, const KRec* __restrict__ krec, KLayout L,
+__global__ void __launch_bounds__(RPT >= 8 ? 256 : 1024) k_apply_single(KTerms<R> T, const KRec* __restrict__ krec, KLayout L,
                                                        const cplx<R>* __restrict__ psi, cplx<R>* __restrict__ out)
 {
     static_assert(RPT <= 12, "row info holds 12 rows");
@@ -479,14 +479,18 @@ ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune)
         const int lim = ((dtype == SYK_C128) ? 12 : 13) - P.log_cw;
         tb = std::max(0, std::min(std::min(tune->tile_bits, M), lim));
     }
-    if (tune && tune->threads > 0) nt_pref = tune->threads;
+    if (tune && tune->threads > 0) nt_pref = P.single ? tune->threads : std::min(256, tune->threads);
     P.tile_bits = tb;
     const int elems = 1 << (tb + P.log_cw);
     const int max_rpt = P.single ? 8 : 16;
     P.nt = std::min(nt_pref, elems);
-    while (elems / P.nt > max_rpt && P.nt < 256) P.nt *= 2;
+    // single kernel: up to 8 rows per thread with <= 256 threads, 4 rows beyond
+    const int max_nt = P.single ? 1024 : 256;
+    auto rpt_cap = [&](int nt) { return (P.single && nt > 256) ? 4 : max_rpt; };
+    while (elems / P.nt > rpt_cap(P.nt) && P.nt < max_nt) P.nt *= 2;
     P.rpt = elems / P.nt;
-    if (P.rpt > max_rpt || P.rpt * P.nt != elems) throw Error(SYK_EINVAL, "apply_H: tile does not fit the launch shape");
+    if (P.rpt > rpt_cap(P.nt) || P.rpt * P.nt != elems)
+        throw Error(SYK_EINVAL, "apply_H: tile does not fit the launch shape");
     P.xcd_remap = tune ? tune->xcd_remap : 1;
     return P;
 }

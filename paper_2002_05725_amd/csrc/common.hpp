@@ -54,7 +54,10 @@ struct DevBuf {
     ~DevBuf() { release(); }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p) {
+            (void)hipDeviceSynchronize();   // work enqueued earlier may still read it
+            (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
     }

@@ -61,25 +61,35 @@ void symmetric_eig(int n, std::vector<double>& a, std::vector<double>& w, std::v
     for (int i = 0; i < n; ++i) w[i] = a[(size_t)i * n + i];
 }
 
-void krylov_step(BlockCtx& c, void* psi, std::complex<double> z, int m, KrylovStats& st)
+// Builds the Krylov basis of psi (V, m vectors in the workspace) and the
+// tridiagonal projection per column.
+LanczosBasis lanczos_build(BlockCtx& c, const void* psi, int m)
 {
     const int B = c.nvec;
     VecOps& ops = c.ops;
     const size_t vb = ops.vec_bytes();
-    char* V = (char*)c.h.ws.get("krylov_V", vb * (size_t)m);
+    LanczosBasis L;
+    L.m = m;
+    L.V = (char*)c.h.ws.get("krylov_V", vb * (size_t)m);
     void* w = c.h.ws.get("krylov_w", vb);
+    char* V = L.V;
 
     std::vector<double> nrm2 = ops.norm2(psi);
-    std::vector<double> nrm(B), inv(B);
+    L.nrm.assign(B, 0.0);
+    std::vector<double> inv(B);
     for (int b = 0; b < B; ++b) {
         if (!std::isfinite(nrm2[b])) throw Error(SYK_EBREAKDOWN, "non-finite norm in Krylov step");
-        nrm[b] = std::sqrt(nrm2[b]);
-        inv[b] = nrm[b] > 0 ? 1.0 / nrm[b] : 0.0;
+        L.nrm[b] = std::sqrt(nrm2[b]);
+        inv[b] = L.nrm[b] > 0 ? 1.0 / L.nrm[b] : 0.0;
     }
     ops.scale(V, psi, inv);
 
-    std::vector<double> alpha((size_t)m * B, 0.0), beta((size_t)m * B, 0.0);
-    std::vector<int> kdim(B, m);
+    L.alpha.assign((size_t)m * B, 0.0);
+    L.beta.assign((size_t)m * B, 0.0);
+    L.kdim.assign(B, m);
+    std::vector<double>& alpha = L.alpha;
+    std::vector<double>& beta = L.beta;
+    std::vector<int>& kdim = L.kdim;
     std::vector<double> scale(B, 0.0);
     for (int j = 0; j < m; ++j) {
         c.apply_H(V + (size_t)j * vb, w);
@@ -97,7 +107,7 @@ void krylov_step(BlockCtx& c, void* psi, std::complex<double> z, int m, KrylovSt
             if (j >= kdim[b]) continue;   // column already invariant: its basis stays zero
             scale[b] = std::max(scale[b], std::fabs(a) + (j > 0 ? beta[(size_t)(j - 1) * B + b] : 0.0));
             if (j < m - 1) {
-                if (bt <= 1e-13 * scale[b] || nrm[b] == 0.0) {
+                if (bt <= 1e-13 * scale[b] || L.nrm[b] == 0.0) {
                     kdim[b] = j + 1;          // invariant subspace: T is exact
                 } else {
                     f[b] = 1.0 / bt;
@@ -106,18 +116,37 @@ void krylov_step(BlockCtx& c, void* psi, std::complex<double> z, int m, KrylovSt
         }
         if (j < m - 1) ops.scale(V + (size_t)(j + 1) * vb, w, f);
     }
+    return L;
+}
+
+void ritz_values(const LanczosBasis& L, int col, int nvec, std::vector<double>& ev, std::vector<double>& S)
+{
+    const int k = L.kdim[col];
+    std::vector<double> T((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i) {
+        T[(size_t)i * k + i] = L.alpha[(size_t)i * nvec + col];
+        if (i + 1 < k) T[(size_t)i * k + i + 1] = T[(size_t)(i + 1) * k + i] = L.beta[(size_t)i * nvec + col];
+    }
+    symmetric_eig(k, T, ev, S);
+}
+
+void krylov_step(BlockCtx& c, void* psi, std::complex<double> z, int m, KrylovStats& st)
+{
+    const int B = c.nvec;
+    LanczosBasis L = lanczos_build(c, psi, m);
+    const std::vector<double>& beta = L.beta;
+    const std::vector<int>& kdim = L.kdim;
+    const std::vector<double>& nrm = L.nrm;
+    char* V = L.V;
+    VecOps& ops = c.ops;
 
     // Per column: y = ||psi|| V S e^{z Lambda} S^T e_1.
     std::vector<zd> coef((size_t)m * B, zd(0.0, 0.0));
     if (st.err.size() != (size_t)B) st.err.assign(B, 0.0);
     for (int b = 0; b < B; ++b) {
         const int k = kdim[b];
-        std::vector<double> T((size_t)k * k, 0.0), ev, S;
-        for (int i = 0; i < k; ++i) {
-            T[(size_t)i * k + i] = alpha[(size_t)i * B + b];
-            if (i + 1 < k) T[(size_t)i * k + i + 1] = T[(size_t)(i + 1) * k + i] = beta[(size_t)i * B + b];
-        }
-        symmetric_eig(k, T, ev, S);
+        std::vector<double> ev, S;
+        ritz_values(L, b, B, ev, S);
         std::vector<zd> g(k);
         for (int l = 0; l < k; ++l) g[l] = std::exp(z * ev[l]) * S[(size_t)0 * k + l];
         for (int i = 0; i < k; ++i) {
@@ -132,6 +161,20 @@ void krylov_step(BlockCtx& c, void* psi, std::complex<double> z, int m, KrylovSt
     }
     ops.combine(psi, V, m, coef);
     ++st.steps;
+}
+
+void lanczos_extremes(BlockCtx& c, const void* psi, int m, double* emin, double* emax)
+{
+    require(c.nvec == 1, "spectrum bounds: one column");
+    LanczosBasis L = lanczos_build(c, psi, m);
+    std::vector<double> ev, S;
+    ritz_values(L, 0, 1, ev, S);
+    *emin = ev[0];
+    *emax = ev[0];
+    for (double e : ev) {
+        *emin = std::min(*emin, e);
+        *emax = std::max(*emax, e);
+    }
 }
 
 void krylov_propagate(BlockCtx& c, void* psi, std::complex<double> z, double total, double step, int m,

@@ -33,6 +33,21 @@ struct KrylovStats {
 // eigenvalues in w, eigenvectors as columns of v (row-major n x n).
 void symmetric_eig(int n, std::vector<double>& a, std::vector<double>& w, std::vector<double>& v);
 
+// Lanczos basis of one step: V (m vectors of the block, workspace), the
+// tridiagonal T per column (alpha: diagonal, beta: off-diagonal, [m][nvec]),
+// the Krylov dimension per column (< m after an invariant subspace) and ||psi||.
+struct LanczosBasis {
+    int m = 0;
+    char* V = nullptr;
+    std::vector<double> alpha, beta, nrm;
+    std::vector<int> kdim;
+};
+LanczosBasis lanczos_build(BlockCtx& c, const void* psi, int m);
+void ritz_values(const LanczosBasis& L, int col, int nvec, std::vector<double>& ev, std::vector<double>& S);
+
+// Smallest and largest Ritz values of m Lanczos steps from psi (one column).
+void lanczos_extremes(BlockCtx& c, const void* psi, int m, double* emin, double* emax);
+
 // psi <- exp(z H) psi per column with one Lanczos step of m vectors.
 void krylov_step(BlockCtx& c, void* psi, std::complex<double> z, int m, KrylovStats& st);
 

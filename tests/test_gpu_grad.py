@@ -1,0 +1,123 @@
+"""Chebyshev forward and the adjoint coupling gradient (HIP path) against the
+CPU checker's forward-mode tangents, central finite differences, and the
+Euler identity sum_k J_k dF/dJ_k = beta dF/dbeta + t dF/dt."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import chebyshev, correlators, jw, krylov
+from paper_2002_05725_amd import api, autograd, inputs
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def _setup(N, seed=0):
+    J = inputs.couplings(N, seed)
+    H = jw.dense_H(N, J)
+    ev = np.linalg.eigvalsh(H)
+    return J, H, 1.1 * max(abs(ev[0]), abs(ev[-1]))
+
+
+@pytest.mark.parametrize("N", [8, 12])
+def test_cheb_forward_vs_checker(N):
+    J, H, e_h = _setup(N)
+    psi = inputs.typical_state(N, 1)
+    T = api.Terms(N, J)
+    o = api.cheb_opts(degree=32, dt=0.1, tau_steps=1, checkpoint_every=10, e_halfwidth=e_h)
+    F = api.cheb_otoc(T, 0, 1, 5.0, 0.6, _gpu(psi), o)
+    maj = lambda a, v: jw.majorana_apply(N, a, v)
+    prop = chebyshev.ChebPropagator(lambda v: H @ v, 0.0, e_h, 32)
+    Fo, _ = chebyshev.otoc(prop, maj, psi, 0, 1, 5.0, 0.6, 0.1)
+    Fe, _, _ = correlators.otoc_estimator(correlators.ExactPropagator(krylov.DenseExp(H)), maj, psi, 0, 1, 5.0, [0.6])
+    assert abs(F - Fo) <= 1e-12
+    assert abs(F - Fe[0]) <= 1e-12
+
+
+@pytest.mark.parametrize("N,beta,tau_steps,ck", [(8, 3.0, 1, 10), (8, 0.0, 1, 3), (10, 5.0, 2, 4)])
+def test_grad_vs_checker_tangent(N, beta, tau_steps, ck):
+    """All couplings against forward-mode tangents of the checker."""
+    J, H, e_h = _setup(N)
+    psi = inputs.typical_state(N, 1)
+    T = api.Terms(N, J)
+    o = api.cheb_opts(degree=24, dt=0.1, tau_steps=tau_steps, checkpoint_every=ck, e_halfwidth=e_h)
+    F, g = api.grad_couplings(T, 0, 1, beta, 0.5, _gpu(psi), o)
+    chis = jw.dense_majoranas(N)
+    maj = lambda a, v: jw.majorana_apply(N, a, v)
+    mvJ = lambda Jx: (lambda v, Hx=jw.dense_H(N, Jx, chis): Hx @ v)
+    qmv = lambda k: (lambda v, Q=jw.dense_quartet(N, k, chis): Q @ v)
+    Fo, go = chebyshev.gradient_tangent(mvJ, qmv, J, maj, psi, 0, 1, beta, 0.5, 0.1, 0.0, e_h, 24,
+                                        list(range(len(J))), tau_steps=tau_steps)
+    assert abs(F - Fo) <= 1e-12
+    assert np.abs(g - go).max() <= 1e-10 * max(1.0, np.abs(go).max())
+
+
+def test_grad_vs_finite_differences_n20():
+    """20 sampled couplings at N=20 against central differences (h = 1e-6) of
+    the GPU forward itself."""
+    N = 20
+    J = inputs.couplings(N, 0)
+    psi = _gpu(inputs.typical_state(N, 1))
+    T = api.Terms(N, J)
+    lo, hi = api.spectrum_bounds(T, psi, 60)
+    e_h = 1.2 * max(abs(lo), abs(hi))
+    o = api.cheb_opts(degree=32, dt=0.1, tau_steps=1, checkpoint_every=10, e_halfwidth=e_h)
+    F, g = api.grad_couplings(T, 0, 1, 5.0, 1.0, psi, o)
+    ks = inputs.quartet_sample(N, 4, 20)
+    h = 1e-6
+    for k in ks:
+        vals = []
+        for s in (1.0, -1.0):
+            Jp = J.copy()
+            Jp[k] += s * h
+            Tp = api.Terms(N, Jp)
+            vals.append(api.cheb_otoc(Tp, 0, 1, 5.0, 1.0, psi, o))
+            Tp.close()
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * np.abs(g).max() + 1e-9
+
+
+def test_grad_euler_identity_n16():
+    N = 16
+    J = inputs.couplings(N, 2)
+    psi = _gpu(inputs.typical_state(N, 3))
+    T = api.Terms(N, J)
+    lo, hi = api.spectrum_bounds(T, psi, 60)
+    e_h = 1.3 * max(abs(lo), abs(hi))
+    beta, t, n = 4.0, 0.8, 8
+    o = api.cheb_opts(degree=40, dt=t / n, tau_steps=2, checkpoint_every=5, e_halfwidth=e_h)
+    F, g = api.grad_couplings(T, 0, 1, beta, t, psi, o)
+    d = 1e-4
+    Fb = [api.cheb_otoc(T, 0, 1, beta + s * d, t, psi, o) for s in (1, -1)]
+    Ft = [api.cheb_otoc(T, 0, 1, beta, t + s * d, psi,
+                        api.cheb_opts(degree=40, dt=(t + s * d) / n, tau_steps=2, checkpoint_every=5, e_halfwidth=e_h))
+          for s in (1, -1)]
+    rhs = beta * (Fb[0] - Fb[1]) / (2 * d) + t * (Ft[0] - Ft[1]) / (2 * d)
+    assert abs(np.dot(J, g) - rhs) <= 1e-7
+
+
+def test_autograd_function_matches():
+    N = 12
+    J, H, e_h = _setup(N, seed=3)
+    psi = _gpu(inputs.typical_state(N, 5))
+    o = api.cheb_opts(degree=24, dt=0.1, tau_steps=1, checkpoint_every=10, e_halfwidth=e_h)
+    F, g = autograd.otoc_value_and_grad(J, N, 0, 1, 2.0, 0.3, psi, o)
+    T = api.Terms(N, J)
+    F2, g2 = api.grad_couplings(T, 0, 1, 2.0, 0.3, psi, o)
+    assert F == F2 and np.array_equal(g, g2)
+    Jt = torch.from_numpy(J)
+    assert abs(float(autograd.ChebOTOC.apply(Jt, N, 0, 1, 2.0, 0.3, psi, o)) - F) == 0.0
+
+
+def test_spectrum_bounds_inside_exact():
+    N = 14
+    J, H, _ = _setup(N)
+    ev = np.linalg.eigvalsh(H)
+    T = api.Terms(N, J)
+    lo, hi = api.spectrum_bounds(T, _gpu(inputs.typical_state(N, 1)), 60)
+    assert ev[0] - 1e-9 <= lo <= ev[0] + 1e-6
+    assert ev[-1] - 1e-6 <= hi <= ev[-1] + 1e-9
