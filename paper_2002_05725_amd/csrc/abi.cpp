@@ -92,23 +92,48 @@ std::vector<float> to_f32(const std::vector<double>& v) { return std::vector<flo
 
 namespace syk {
 
-const Group* HamiltonianDev::groups_for(int tile_bits) const
+const Group* HamiltonianDev::groups_for(int tile_bits, bool split_far) const
 {
-    auto it = groups.find(tile_bits);
+    const int key = tile_bits * 2 + (split_far ? 1 : 0);
+    auto it = groups.find(key);
     if (it == groups.end()) {
-        std::vector<Group> g = make_groups(*host_masks, tile_bits);
+        std::vector<uint32_t> far;
+        std::vector<Group> g = make_groups(*host_masks, tile_bits, split_far ? &far : nullptr);
         std::unique_ptr<DevBuf> b(new DevBuf());
         upload(*b, g);
-        n_groups[tile_bits] = (int)g.size();
-        it = groups.emplace(tile_bits, std::move(b)).first;
+        n_groups[key] = (int)g.size();
+        it = groups.emplace(key, std::move(b)).first;
+        if (split_far) {
+            std::vector<FarRec> fr;
+            for (uint32_t i : far) {
+                const MaskRec& m = (*host_masks)[i];
+                fr.push_back({m.x >> tile_bits, m.qpack, m.zbase, m.type_tab & 0x0fffffffu});
+            }
+            std::unique_ptr<DevBuf> fb(new DevBuf());
+            upload(*fb, fr);
+            n_fars[tile_bits] = (int)fr.size();
+            fars[tile_bits] = std::move(fb);
+        }
     }
     return it->second->as<Group>();
 }
 
-int HamiltonianDev::n_groups_for(int tile_bits) const
+int HamiltonianDev::n_groups_for(int tile_bits, bool split_far) const
 {
-    groups_for(tile_bits);
-    return n_groups.at(tile_bits);
+    groups_for(tile_bits, split_far);
+    return n_groups.at(tile_bits * 2 + (split_far ? 1 : 0));
+}
+
+const FarRec* HamiltonianDev::far_for(int tile_bits) const
+{
+    groups_for(tile_bits, true);
+    return fars.at(tile_bits)->as<FarRec>();
+}
+
+int HamiltonianDev::n_far_for(int tile_bits) const
+{
+    groups_for(tile_bits, true);
+    return n_fars.at(tile_bits);
 }
 
 }  // namespace syk

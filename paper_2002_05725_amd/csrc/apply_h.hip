@@ -35,6 +35,8 @@ struct KTerms {
 };
 
 struct KLayout {
+    const FarRec* __restrict__ far;   // single kernel: QUAD masks flipping only tile bits
+    int n_far;
     int tile_bits;     // rows per tile = 2^tile_bits
     int log_cw;        // columns per tile = 2^log_cw
     int64_t ld;        // row stride of psi/out in elements (= nvec)
@@ -106,11 +108,16 @@ __global__ void __launch_bounds__(RPT >= 8 ? 256 : 1024) k_apply_single(KTerms<R
     constexpr bool kSplit = sizeof(R) < sizeof(double);
     double acc_re[RPT], acc_im[RPT];
     R pr[RPT], pi[RPT];
+    uint32_t roff[RPT];   // LDS byte offset of the thread's rows
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         acc_re[k] = acc_im[k] = 0.0;
         pr[k] = pi[k] = R(0);
+        roff[k] = (tid + k * nt) * (uint32_t)sizeof(cplx<R>);
     }
+    auto lds = [&](uint32_t byte_off) -> cplx<R> {
+        return *reinterpret_cast<const cplx<R>*>(smem_raw + byte_off);
+    };
 
     for (int g = 0; g < T.n_groups; ++g) {
         const Group G = T.groups[g];
@@ -137,6 +144,7 @@ __global__ void __launch_bounds__(RPT >= 8 ? 256 : 1024) k_apply_single(KTerms<R
             const KRec m = krec[mi];
             const uint32_t type = m.meta >> 28;
             const uint32_t tab = m.meta & 0x03ffffffu;
+            const uint32_t xlb = m.xl * (uint32_t)sizeof(cplx<R>);
             if (type == MASK_QUAD) {
                 const uint32_t path = (m.meta >> 26) & 3u;
                 const cplx<R>* tq = tabs + (tab - G.quad_first) * 16;
@@ -149,7 +157,7 @@ __global__ void __launch_bounds__(RPT >= 8 ? 256 : 1024) k_apply_single(KTerms<R
                     for (int k = 0; k < RPT; ++k) {
                         const uint32_t sk = (path == PATH_SIGN) ? (m.kinfo[k / 6] >> (5 * (k % 6) + 4)) & 1u : 0u;
                         const R a = flip(tr, sk), b = flip(ti, sk);
-                        const cplx<R> v = src[(tid + k * nt) ^ m.xl];
+                        const cplx<R> v = lds(roff[k] ^ xlb);
                         pr[k] = fma(a, v.re, pr[k]);
                         pr[k] = fma(-b, v.im, pr[k]);
                         pi[k] = fma(a, v.im, pi[k]);
@@ -162,7 +170,7 @@ __global__ void __launch_bounds__(RPT >= 8 ? 256 : 1024) k_apply_single(KTerms<R
                         const cplx<R> t = tq[il | (ki & 15u)];
                         const uint32_t s = sl ^ (ki >> 4);
                         const R a = flip(t.re, s), b = flip(t.im, s);
-                        const cplx<R> v = src[(tid + k * nt) ^ m.xl];
+                        const cplx<R> v = lds(roff[k] ^ xlb);
                         pr[k] = fma(a, v.re, pr[k]);
                         pr[k] = fma(-b, v.im, pr[k]);
                         pi[k] = fma(a, v.im, pi[k]);
@@ -206,7 +214,7 @@ __global__ void __launch_bounds__(RPT >= 8 ? 256 : 1024) k_apply_single(KTerms<R
                     const uint32_t s = sl ^ parity(ru & m.zbase);
                     const R dre = flip(ph[0].re * k0 + ph[1].re * k1 + ph[2].re * k2 + ph[3].re * k3, s);
                     const R dim = flip(ph[0].im * k0 + ph[1].im * k1 + ph[2].im * k2 + ph[3].im * k3, s);
-                    const cplx<R> v = src[(tid + k * nt) ^ m.xl];
+                    const cplx<R> v = lds(roff[k] ^ xlb);
                     pr[k] = fma(dre, v.re, pr[k]);
                     pr[k] = fma(-dim, v.im, pr[k]);
                     pi[k] = fma(dre, v.im, pi[k]);
@@ -217,11 +225,60 @@ __global__ void __launch_bounds__(RPT >= 8 ? 256 : 1024) k_apply_single(KTerms<R
 #pragma unroll
                 for (int k = 0; k < RPT; ++k) {
                     const uint32_t r = base | (tid + k * nt);
-                    const cplx<R> v = src[(tid + k * nt) ^ m.xl];
+                    const cplx<R> v = lds(roff[k] ^ xlb);
                     R s = R(0);
                     for (int n = 0; n < T.n_diag; ++n) s += flip(d[n], parity(r & T.dz[n]));
                     pr[k] = fma(s, v.re, pr[k]);
                     pi[k] = fma(s, v.im, pi[k]);
+                }
+            }
+        }
+        if (kSplit) {
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) {
+                acc_re[k] += (double)pr[k];
+                acc_im[k] += (double)pi[k];
+                pr[k] = pi[k] = R(0);
+            }
+        }
+    }
+
+    // QUAD masks that flip only tile bits: D_x is one number per tile, the
+    // source rows are the same rows of tile ^ x_high.  Streamed straight from
+    // global memory with the next mask's rows loaded one mask ahead.
+    if (L.n_far > 0) {
+        cplx<R> vn[RPT];
+        FarRec fn = L.far[0];
+        const cplx<R>* sp = psi + ((uint64_t)(tile ^ fn.x_high) << L.tile_bits);
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) vn[k] = sp[tid + k * nt];
+        for (int f = 0; f < L.n_far; ++f) {
+            const FarRec fc = fn;
+            cplx<R> v[RPT];
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) v[k] = vn[k];
+            if (f + 1 < L.n_far) {
+                fn = L.far[f + 1];
+                sp = psi + ((uint64_t)(tile ^ fn.x_high) << L.tile_bits);
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) vn[k] = sp[tid + k * nt];
+            }
+            const cplx<R> t = T.tab4[((size_t)fc.tab * T.n_real + rc) * 16 + quad_index(base, fc.qpack)];
+            const uint32_t s = parity(base & fc.zbase);
+            const R tr = flip(t.re, s), ti = flip(t.im, s);
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) {
+                pr[k] = fma(tr, v[k].re, pr[k]);
+                pr[k] = fma(-ti, v[k].im, pr[k]);
+                pi[k] = fma(tr, v[k].im, pi[k]);
+                pi[k] = fma(ti, v[k].re, pi[k]);
+            }
+            if (kSplit && (f & 63) == 63) {
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) {
+                    acc_re[k] += (double)pr[k];
+                    acc_im[k] += (double)pi[k];
+                    pr[k] = pi[k] = R(0);
                 }
             }
         }
@@ -466,14 +523,14 @@ ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune)
     P.log_cw = ilog2(cw);
     P.slices = nvec / cw;
     P.single = (nvec == 1);
-    // 1024-row source tiles (16 KiB complex128, 8 KiB complex64): measured best
-    // at N=44 and N=52 on MI355X.
-    const int max_elems_log = 10;
+    // Single vector: 2048-row source tiles with 512 threads (4 rows each);
+    // blocks: 1024 elements per tile.  Measured best at N=44 and N=52.
+    const int max_elems_log = P.single ? 11 : 10;
     int tb = std::min(M, max_elems_log - P.log_cw);
     if (tb < 0) tb = 0;
     // Keep enough workgroups to fill 256 CUs several times over.
     while (tb > 0 && ((int64_t)1 << (M - tb)) * P.slices < 2048 && ((int64_t)1 << (tb + P.log_cw)) > 256) --tb;
-    int nt_pref = 256;
+    int nt_pref = P.single ? 512 : 256;
     if (tune && tune->tile_bits > 0) {
         // at most 64 KiB of LDS per tile
         const int lim = ((dtype == SYK_C128) ? 12 : 13) - P.log_cw;
@@ -499,8 +556,10 @@ void launch_apply_h(const HamiltonianDev& H, syk_dtype dtype, int nvec, const in
                     const void* psi, void* out, const ApplyPlan& P, hipStream_t s)
 {
     const int M = H.M;
-    const Group* groups = H.groups_for(P.tile_bits);
-    const int n_groups = H.n_groups_for(P.tile_bits);
+    const Group* groups = H.groups_for(P.tile_bits, P.single);
+    const int n_groups = H.n_groups_for(P.tile_bits, P.single);
+    const FarRec* far = P.single ? H.far_for(P.tile_bits) : nullptr;
+    const int n_far = P.single ? H.n_far_for(P.tile_bits) : 0;
     const int cw = 1 << P.log_cw;
     const KRec* krec = P.single ? krecs_for(H, P) : nullptr;
     timing_begin(s);
@@ -512,6 +571,8 @@ void launch_apply_h(const HamiltonianDev& H, syk_dtype dtype, int nvec, const in
         L.col0 = sl * cw;
         L.n_tiles = (uint32_t)(((uint64_t)1 << M) >> P.tile_bits);
         L.xcd_remap = P.xcd_remap;
+        L.far = far;
+        L.n_far = n_far;
         for (int c = 0; c < cw; ++c) L.real[c] = real_of_col ? real_of_col[L.col0 + c] : 0;
         if (dtype == SYK_C128) {
             KTerms<double> T{H.masks, groups, H.tab4_d, H.qinfo, H.phi2_d, H.w2_d, H.dz, H.dw_d,

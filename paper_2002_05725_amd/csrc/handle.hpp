@@ -28,8 +28,14 @@ struct HamiltonianDev {
     const std::vector<uint64_t>* bin_off = nullptr;
     mutable std::map<int, std::unique_ptr<DevBuf>> groups;
     mutable std::map<int, int> n_groups;
-    const Group* groups_for(int tile_bits) const;
-    int n_groups_for(int tile_bits) const;
+    // Chunks for a tile size; with split_far, QUAD masks that flip only tile
+    // bits are listed separately (far_for).
+    const Group* groups_for(int tile_bits, bool split_far = false) const;
+    int n_groups_for(int tile_bits, bool split_far = false) const;
+    const FarRec* far_for(int tile_bits) const;
+    int n_far_for(int tile_bits) const;
+    mutable std::map<int, std::unique_ptr<DevBuf>> fars;
+    mutable std::map<int, int> n_fars;
     // Per-launch-shape mask records of the single-vector kernel, built on first use.
     mutable std::map<int, std::unique_ptr<DevBuf>> krecs;
 };

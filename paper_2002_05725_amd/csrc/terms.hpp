@@ -110,6 +110,14 @@ struct DeviceTerms {
     DevBuf masks, tab4_d, tab4_f, qinfo, phi2_d, phi2_f, w2_d, w2_f, dz, dw_d, dw_f;
 };
 
-std::vector<Group> make_groups(const std::vector<MaskRec>& masks, int tile_bits);
+// Chunks for tiles of 2^tile_bits rows.  With `far`, QUAD masks that flip no
+// row inside a tile are left out of the chunks and their indices appended to
+// *far instead (their coefficient is constant over a tile).
+std::vector<Group> make_groups(const std::vector<MaskRec>& masks, int tile_bits, std::vector<uint32_t>* far = nullptr);
+
+// A QUAD mask whose flipped qubits are all tile bits.
+struct alignas(16) FarRec {
+    uint32_t x_high, qpack, zbase, tab;
+};
 
 }  // namespace syk
