@@ -251,7 +251,10 @@ void grad_bins(syk_terms_s& h, const std::vector<const void*>& g, const std::vec
     const int npairs = (int)g.size();
     if (npairs == 0) return;
     require(npairs <= 64 && (int)v.size() == npairs && (int)w.size() == npairs, "gradient: bad pair list");
-    const ApplyPlan P = plan_apply(H.M, 1, SYK_C128, nullptr);   // default shape: <= 256 threads
+    // 1024-row tiles, 256 threads (the kernel's launch bound)
+    const ApplyTuning tune{10, 256, 1};
+    const ApplyPlan P = plan_apply(H.M, 1, SYK_C128, &tune);
+    require(P.nt <= 256, "gradient: launch shape");
     const KRec* krec = krecs_for(H, P);
     auto it = h.grad_chunks.find(P.tile_bits);
     if (it == h.grad_chunks.end()) {
