@@ -6,9 +6,11 @@ time step of the OTOC propagation (m = 12 applications of H, two-pass
 Gram-Schmidt with FP64 inner products, FP64 tridiagonal exponential, basis
 combination) of one complex128 state by dt = 0.25.
 
-Printed: one JSON line with the OTOC time-steps/s (value), the apply_H
-roofline figure (algorithmic bytes of one apply over its HIP-event-timed
-duration, against 8 TB/s), the complex64 leg, and the CPU checker timed on a
+Printed: one JSON line with the OTOC time-steps/s (value); the apply_H figures
+(algorithmic bytes of one apply over its HIP-event-timed duration, against
+8 TB/s, in "apply_H"; the same duration against the ALU issue roof in
+"roofline", with the rocprofv3-measured HBM bytes when they were taken on the
+current kernel source); the complex64 leg; and the CPU checker timed on a
 bounded sample of rows of the same apply.
 """
 from __future__ import annotations
@@ -25,6 +27,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# ALU roof of apply_H: 256 CUs x 64 lanes x 2.4 GHz lane-operations per second
+# (an FP64 FMA issues at the INT32 rate on gfx950: 78.6 TFLOP/s = 39.3 T FMA/s).
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Elementary operations per (row, flip mask) of the grouped product: source
+# index r ^ x (1), the four table-index bits (4), the sign parity of r & zbase
+# (2), and the complex multiply-accumulate (4 FMA).
+OPS_PER_PAIR = 11
 METRIC = "apply_H GB/s (% HBM peak) and OTOC time-steps/s at N=52; grad/fwd cost ratio"
 
 
@@ -78,8 +87,8 @@ def cpu_baseline(N, J, psi_host, m, target_s):
     from oracle import native
     D = psi_host.size
     t0 = time.perf_counter()
-    native.apply_range(N, J, psi_host, 0, 256)          # calibration
-    rate = 256 / max(time.perf_counter() - t0, 1e-6)
+    native.apply_range(N, J, psi_host, 0, 4096)         # calibration
+    rate = 4096 / max(time.perf_counter() - t0, 1e-6)
     rows = int(min(D, max(256, rate * target_s)))
     t0 = time.perf_counter()
     native.apply_range(N, J, psi_host, 0, rows)
@@ -105,7 +114,7 @@ def main():
     ap.add_argument("--m", type=int, default=12)
     ap.add_argument("--dt", type=float, default=0.25)
     ap.add_argument("--c64-steps", type=int, default=1)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-apply", type=int, default=0,
                     help="only run this many complex128 apply_H calls and one 1 GiB device copy "
@@ -155,6 +164,7 @@ def main():
     avg_apply_s = apply_ms / n_apply / 1e3
     alg_bytes = (T.n_masks + 1) * D * 16
     achieved = alg_bytes / avg_apply_s / 1e9
+    alu_tops = OPS_PER_PAIR * T.n_masks * D / avg_apply_s / 1e12
     log(f"[bench] c128: {ms_step:.0f} ms/step, apply {avg_apply_s * 1e3:.1f} ms ({achieved:.0f} GB/s alg)")
 
     c64 = None
@@ -203,12 +213,14 @@ def main():
             "bytes_model": "(n_masks + 1) * dim * 16 B",
         },
         "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "bound": "alu",
+            "achieved": alu_tops,
+            "peak": ALU_PEAK_TOPS,
+            "unit": "TOP/s",
+            "frac": alu_tops / ALU_PEAK_TOPS,
             "traffic": traffic,
+            "ops_model": f"{OPS_PER_PAIR} lane-operations per (row, flip mask) pair, n_masks * dim pairs",
+            "traffic_unit": "bytes per apply (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },
         "complex64": c64,
     }
