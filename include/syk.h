@@ -14,8 +14,8 @@
  *  - States.  A state of N Majoranas has dim = 2^(N/2) complex entries.  Qubit
  *    k is bit k of the basis index; Y = [[0,-i],[i,0]].  Entries are
  *    interleaved (re, im) pairs: complex128 (SYK_C128) or complex64 (SYK_C64).
- *  - Blocks.  nvec >= 1 states are stored as one row-major [dim][nvec]
- *    array: entry (r, c) is element r*nvec + c.  nvec = 1 is a plain vector.
+ *  - Blocks.  nvec >= 1 states (columns) are stored one after another:
+ *    entry (r, c) is element c*dim + r.  nvec = 1 is a plain vector.
  *    real_of_col (host, nvec entries, or NULL meaning all zeros) names the
  *    coupling realisation used by each column.
  *  - Couplings.  J holds n_real realisations back to back, each C(N,4) FP64
@@ -82,7 +82,8 @@ syk_status syk_terms_info(syk_terms t, int* N, int* n_real, int64_t* dim, int64_
 /*
  * out = H psi column by column (matrix-free product, SI "Krylov subspace
  * methods": the product is formed on the fly from the symbolic terms).
- * psi, out: device [dim][nvec] of `dtype`; out must not overlap psi.
+ * psi, out: device, nvec columns of dim entries of `dtype`; out must not
+ * overlap psi.  Columns are served by one launch per 64 columns.
  * Column c uses realisation real_of_col[c].  complex64 stores and multiplies
  * in FP32 and sums each row in FP64 across flip groups.
  */
@@ -147,7 +148,7 @@ syk_status syk_krylov_expmv(syk_terms t, syk_dtype dtype, int nvec, const int32_
  * typicality formula of SI "Disorder averaging"):
  *   G(t) = <psi| rho^{1/2} chi_i(t) chi_i rho^{1/2} |psi> / Z,
  *   Z = <psi|rho|psi>, rho = e^{-beta H}, chi(t) = e^{iHt} chi e^{-iHt}.
- * t: host, nt >= 1 ascending values >= 0.  psi0: device [dim][nvec].
+ * t: host, nt >= 1 ascending values >= 0.  psi0: device, nvec columns.
  * G: host [nt][nvec] (re, im) pairs; G_R(t) = 2 Re G.  Z: host [nvec] or NULL.
  */
 syk_status syk_two_point(syk_terms t, syk_dtype dtype, int i, double beta, const double* times,
@@ -162,7 +163,7 @@ syk_status syk_two_point(syk_terms t, syk_dtype dtype, int i, double beta, const
  * averaging") with the trace cut symmetrically.  Forward legs e^{-iHt} are
  * advanced incrementally from one output time to the next; each output time
  * then propagates back by its full t.
- * t: host, nt >= 1 ascending values >= 0.  psi0: device [dim][nvec].
+ * t: host, nt >= 1 ascending values >= 0.  psi0: device, nvec columns.
  * F: host [nt][nvec]; F_im (may be NULL): the imaginary part, a typicality
  * diagnostic; Z: host [nvec] or NULL.
  */

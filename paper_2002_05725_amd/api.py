@@ -3,7 +3,7 @@ tensors for device memory and streams.  Argument marshalling only; every step
 of the computation runs in the HIP library.
 
 States are complex torch tensors on the GPU, shape [dim] (one vector) or
-[dim, nvec] (a block, row-major as the library expects).
+[nvec, dim] (a block of nvec states, each row one state, as the library expects).
 """
 from __future__ import annotations
 
@@ -28,8 +28,8 @@ def _nvec(t: torch.Tensor) -> int:
     if t.dim() == 1:
         return 1
     if t.dim() == 2:
-        return int(t.shape[1])
-    raise ValueError("states must have shape [dim] or [dim, nvec]")
+        return int(t.shape[0])
+    raise ValueError("states must have shape [dim] or [nvec, dim]")
 
 
 def _check_state(t: torch.Tensor, dim: int, name: str):
@@ -37,8 +37,8 @@ def _check_state(t: torch.Tensor, dim: int, name: str):
         raise ValueError(f"{name} must be a GPU tensor")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
-    if t.shape[0] != dim:
-        raise ValueError(f"{name} has {t.shape[0]} rows, expected {dim}")
+    if t.dim() not in (1, 2) or t.shape[-1] != dim:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected [{dim}] or [nvec, {dim}]")
 
 
 def _stream() -> ctypes.c_void_p:
@@ -148,7 +148,7 @@ def dot(a: torch.Tensor, b: torch.Tensor) -> np.ndarray:
         raise ValueError("a and b must have equal shape and dtype")
     nvec = _nvec(a)
     out = np.empty(2 * nvec, dtype=np.float64)
-    check(lib().syk_dot(_dtype_code(a), int(a.shape[0]), nvec, ctypes.c_void_p(a.data_ptr()),
+    check(lib().syk_dot(_dtype_code(a), int(a.shape[-1]), nvec, ctypes.c_void_p(a.data_ptr()),
                         ctypes.c_void_p(b.data_ptr()), out.ctypes.data_as(ctypes.c_void_p), _stream()), "syk_dot")
     return out[0::2] + 1j * out[1::2]
 

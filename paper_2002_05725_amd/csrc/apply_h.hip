@@ -1,19 +1,18 @@
 // Matrix-free H psi for the Jordan-Wigner SYK Hamiltonian on gfx950.
 //
 // (H psi)[r] = sum_x D_x(r) psi[r ^ x] over the flip masks x of terms.hpp.
-// A workgroup owns one tile of 2^tile_bits consecutive rows (times up to 64
-// interleaved columns of a block).  For a mask, every row of the tile reads
+// A workgroup owns one tile of 2^tile_bits consecutive rows of one column of a
+// block (columns are whole state vectors, one after another).  For a mask, every row of the tile reads
 // the tile (tile ^ (x >> tile_bits)) of psi, permuted by x's low bits, so the
 // masks are processed chunk by chunk in x order: the shared source tile is
 // staged once into LDS with coalesced loads, every mask of the chunk gathers
 // from LDS, and each thread keeps its rows' sums in registers and writes them
 // once.
 //
-// Two kernels:
-//  * k_apply_single: one column, one realisation.  Mask records, PAIR weights
-//    and DIAG terms are wave-uniform (scalar loads); the chunk's QUAD tables are
-//    staged into LDS next to the source tile.
-//  * k_apply_block: up to 64 interleaved columns, each with its realisation.
+// Grid: (tiles, columns); every workgroup serves one column and that column's
+// realisation, so mask records, PAIR weights and DIAG terms are wave-uniform
+// (scalar loads) and the chunk's QUAD tables are staged into LDS next to the
+// source tile.  Up to 64 columns per launch.
 #include "apply_h.hpp"
 #include "timing.hpp"
 
@@ -35,16 +34,17 @@ struct KTerms {
 };
 
 struct KLayout {
-    const FarRec* __restrict__ far;   // single kernel: QUAD masks flipping only tile bits
+    const FarRec* __restrict__ far;   // QUAD masks flipping only tile bits
     int n_far;
     int tile_bits;     // rows per tile = 2^tile_bits
-    int log_cw;        // columns per tile = 2^log_cw
-    int64_t ld;        // row stride of psi/out in elements (= nvec)
-    int col0;          // first column of this launch
+    uint64_t dim;      // rows per column
+    int col0;          // first column of this launch (column = col0 + blockIdx.y)
     uint32_t n_tiles;  // dim >> tile_bits
     int xcd_remap;     // spread consecutive tiles over XCDs in contiguous ranges
-    int32_t real[64];  // realisation of each column of the slice
+    int32_t real[kColsPerLaunch];  // realisation of each column of the launch
 };
+
+static_assert(kColsPerLaunch == 64, "column slice");
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give XCD j the
 // contiguous tile range [j n/8, (j+1) n/8) so that its L2 sees neighbouring
@@ -99,9 +99,11 @@ __global__ void __launch_bounds__(RPT >= 8 ? 256 : 1024) k_apply_single(KTerms<R
     const uint32_t row_mask = (1u << L.tile_bits) - 1u;
     const uint32_t kmask = row_mask & ~(nt - 1u);       // row bits that vary with k
     const uint32_t tid = threadIdx.x;
-    const int rc = L.real[0];
+    const int rc = L.real[blockIdx.y];
     const int M = T.M;
     const uint32_t base = tile << L.tile_bits;
+    psi += (uint64_t)(L.col0 + blockIdx.y) * L.dim;   // this workgroup's column
+    out += (uint64_t)(L.col0 + blockIdx.y) * L.dim;
 
     // complex128 sums directly in pr/pi; complex64 sums each chunk in FP32 and
     // carries the running total in FP64.
@@ -300,131 +302,6 @@ __global__ void __launch_bounds__(RPT >= 8 ? 256 : 1024) k_apply_single(KTerms<R
     }
 }
 
-template <typename R, int RPT>
-__global__ void __launch_bounds__(256) k_apply_block(KTerms<R> T, KLayout L, const cplx<R>* __restrict__ psi,
-                                                      cplx<R>* __restrict__ out)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R>* src = reinterpret_cast<cplx<R>*>(smem_raw);
-
-    const int nt = blockDim.x;
-    const int cw_mask = (1 << L.log_cw) - 1;
-    const uint32_t tile = tile_of_block(blockIdx.x, L);
-    const uint32_t row_mask = (1u << L.tile_bits) - 1u;
-
-    int lin[RPT];
-    uint32_t row[RPT];
-    int col[RPT];
-    int rc[RPT];
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        lin[k] = threadIdx.x + k * nt;
-        col[k] = lin[k] & cw_mask;
-        row[k] = (tile << L.tile_bits) | (uint32_t)(lin[k] >> L.log_cw);
-        int r = 0;
-        for (int c = 0; c <= cw_mask; ++c)
-            if (c == col[k]) r = L.real[c];
-        rc[k] = r;
-    }
-
-    double acc_re[RPT], acc_im[RPT];
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) acc_re[k] = acc_im[k] = 0.0;
-
-    const int M = T.M;
-    for (int g = 0; g < T.n_groups; ++g) {
-        const Group G = T.groups[g];
-        if (G.new_tile) {
-            const uint32_t stile = tile ^ G.x_high;
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < RPT; ++k) {
-                const uint64_t srow = ((uint64_t)stile << L.tile_bits) | (uint32_t)(lin[k] >> L.log_cw);
-                src[lin[k]] = psi[srow * L.ld + L.col0 + col[k]];
-            }
-            __syncthreads();
-        }
-
-        R pr[RPT], pi[RPT];
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) pr[k] = pi[k] = R(0);
-
-        for (uint32_t mi = G.first; mi < G.first + G.count; ++mi) {
-            const MaskRec m = T.masks[mi];
-            const int xl_sh = (int)((m.x & row_mask) << L.log_cw);
-            const uint32_t type = m.type_tab >> 28;
-            const uint32_t tab = m.type_tab & 0x0fffffffu;
-            if (type == MASK_QUAD) {
-#pragma unroll
-                for (int k = 0; k < RPT; ++k) {
-                    const cplx<R> v = src[lin[k] ^ xl_sh];
-                    const uint32_t r = row[k];
-                    const uint32_t idx = quad_index(r, m.qpack);
-                    const cplx<R> t = T.tab4[((size_t)tab * T.n_real + rc[k]) * 16 + idx];
-                    const uint32_t s = parity(r & m.zbase);
-                    const R tr = flip(t.re, s), ti = flip(t.im, s);
-                    pr[k] = fma(tr, v.re, pr[k]);
-                    pr[k] = fma(-ti, v.im, pr[k]);
-                    pi[k] = fma(tr, v.im, pi[k]);
-                    pi[k] = fma(ti, v.re, pi[k]);
-                }
-            } else if (type == MASK_PAIR) {
-                const cplx<R>* ph = T.phi2 + (size_t)tab * 16 + 12;
-#pragma unroll
-                for (int k = 0; k < RPT; ++k) {
-                    const cplx<R> v = src[lin[k] ^ xl_sh];
-                    const uint32_t r = row[k];
-                    const R* w = T.w2 + ((size_t)tab * T.n_real + rc[k]) * 4 * (M + 1);
-                    R l0 = w[M], l1 = w[(M + 1) + M], l2 = w[2 * (M + 1) + M], l3 = w[3 * (M + 1) + M];
-                    for (int c = 0; c < M; ++c) {
-                        const R b = (R)bit(r, c);
-                        l0 = fma(w[c], b, l0);
-                        l1 = fma(w[(M + 1) + c], b, l1);
-                        l2 = fma(w[2 * (M + 1) + c], b, l2);
-                        l3 = fma(w[3 * (M + 1) + c], b, l3);
-                    }
-                    const uint32_t sa = bit(r, mask_q(m.qpack, 0)) ^ 1u, sb = bit(r, mask_q(m.qpack, 1)) ^ 1u;
-                    l1 = flip(l1, sa);
-                    l2 = flip(l2, sb);
-                    l3 = flip(l3, sa ^ sb);
-                    R dre = ph[0].re * l0 + ph[1].re * l1 + ph[2].re * l2 + ph[3].re * l3;
-                    R dim = ph[0].im * l0 + ph[1].im * l1 + ph[2].im * l2 + ph[3].im * l3;
-                    const uint32_t s = parity(r & m.zbase);
-                    dre = flip(dre, s);
-                    dim = flip(dim, s);
-                    pr[k] = fma(dre, v.re, pr[k]);
-                    pr[k] = fma(-dim, v.im, pr[k]);
-                    pi[k] = fma(dre, v.im, pi[k]);
-                    pi[k] = fma(dim, v.re, pi[k]);
-                }
-            } else {  // MASK_DIAG
-#pragma unroll
-                for (int k = 0; k < RPT; ++k) {
-                    const cplx<R> v = src[lin[k] ^ xl_sh];
-                    const uint32_t r = row[k];
-                    const R* d = T.dw + (size_t)rc[k] * T.n_diag;
-                    R s = R(0);
-                    for (int n = 0; n < T.n_diag; ++n) s += flip(d[n], parity(r & T.dz[n]));
-                    pr[k] = fma(s, v.re, pr[k]);
-                    pi[k] = fma(s, v.im, pi[k]);
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            acc_re[k] += (double)pr[k];
-            acc_im[k] += (double)pi[k];
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        cplx<R> o;
-        o.re = (R)acc_re[k];
-        o.im = (R)acc_im[k];
-        out[(uint64_t)row[k] * L.ld + L.col0 + col[k]] = o;
-    }
-}
-
 inline int ilog2(int64_t v)
 {
     int l = 0;
@@ -433,31 +310,19 @@ inline int ilog2(int64_t v)
 }
 
 template <typename R>
-void launch_t(const ApplyPlan& P, const KTerms<R>& T, const KRec* krec, KLayout L, const void* psi, void* out,
-              hipStream_t s)
+void launch_t(const ApplyPlan& P, const KTerms<R>& T, const KRec* krec, KLayout L, int ncols, const void* psi,
+              void* out, hipStream_t s)
 {
-    dim3 grid(L.n_tiles), block(P.nt);
-    const size_t tile = ((size_t)1 << (P.tile_bits + P.log_cw)) * sizeof(cplx<R>);
+    dim3 grid(L.n_tiles, ncols), block(P.nt);
+    const size_t lds = ((size_t)1 << P.tile_bits) * sizeof(cplx<R>) + (size_t)kChunkMasks * 16 * sizeof(cplx<R>);
     auto* in = static_cast<const cplx<R>*>(psi);
     auto* o = static_cast<cplx<R>*>(out);
-    if (P.single) {
-        const size_t lds = tile + (size_t)kChunkMasks * 16 * sizeof(cplx<R>);
-        switch (P.rpt) {
-        case 1: hipLaunchKernelGGL((k_apply_single<R, 1>), grid, block, lds, s, T, krec, L, in, o); break;
-        case 2: hipLaunchKernelGGL((k_apply_single<R, 2>), grid, block, lds, s, T, krec, L, in, o); break;
-        case 4: hipLaunchKernelGGL((k_apply_single<R, 4>), grid, block, lds, s, T, krec, L, in, o); break;
-        case 8: hipLaunchKernelGGL((k_apply_single<R, 8>), grid, block, lds, s, T, krec, L, in, o); break;
-        default: throw Error(SYK_EINVAL, "apply_H: unsupported rows per thread");
-        }
-    } else {
-        switch (P.rpt) {
-        case 1: hipLaunchKernelGGL((k_apply_block<R, 1>), grid, block, tile, s, T, L, in, o); break;
-        case 2: hipLaunchKernelGGL((k_apply_block<R, 2>), grid, block, tile, s, T, L, in, o); break;
-        case 4: hipLaunchKernelGGL((k_apply_block<R, 4>), grid, block, tile, s, T, L, in, o); break;
-        case 8: hipLaunchKernelGGL((k_apply_block<R, 8>), grid, block, tile, s, T, L, in, o); break;
-        case 16: hipLaunchKernelGGL((k_apply_block<R, 16>), grid, block, tile, s, T, L, in, o); break;
-        default: throw Error(SYK_EINVAL, "apply_H: unsupported rows per thread");
-        }
+    switch (P.rpt) {
+    case 1: hipLaunchKernelGGL((k_apply_single<R, 1>), grid, block, lds, s, T, krec, L, in, o); break;
+    case 2: hipLaunchKernelGGL((k_apply_single<R, 2>), grid, block, lds, s, T, krec, L, in, o); break;
+    case 4: hipLaunchKernelGGL((k_apply_single<R, 4>), grid, block, lds, s, T, krec, L, in, o); break;
+    case 8: hipLaunchKernelGGL((k_apply_single<R, 8>), grid, block, lds, s, T, krec, L, in, o); break;
+    default: throw Error(SYK_EINVAL, "apply_H: unsupported rows per thread");
     }
     SYK_HIP(hipGetLastError());
 }
@@ -517,34 +382,24 @@ const KRec* krecs_for(const HamiltonianDev& H, const ApplyPlan& P)
 ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune)
 {
     ApplyPlan P{};
-    int cw = 1;
-    if (nvec <= 64 && (nvec & (nvec - 1)) == 0) cw = nvec;
-    else if (nvec % 64 == 0) cw = 64;
-    P.log_cw = ilog2(cw);
-    P.slices = nvec / cw;
-    P.single = (nvec == 1);
-    // Single vector: 2048-row source tiles with 512 threads (4 rows each);
-    // blocks: 1024 elements per tile.  Measured best at N=44 and N=52.
-    const int max_elems_log = P.single ? 11 : 10;
-    int tb = std::min(M, max_elems_log - P.log_cw);
-    if (tb < 0) tb = 0;
-    // Keep enough workgroups to fill 256 CUs several times over.
-    while (tb > 0 && ((int64_t)1 << (M - tb)) * P.slices < 2048 && ((int64_t)1 << (tb + P.log_cw)) > 256) --tb;
-    int nt_pref = P.single ? 512 : 256;
+    P.slices = (nvec + kColsPerLaunch - 1) / kColsPerLaunch;
+    // 2048-row source tiles with 512 threads (4 rows each): measured best at
+    // N=44 and N=52; smaller tiles when the columns would not fill the chip.
+    int tb = std::min(M, 11);
+    while (tb > 8 && ((int64_t)1 << (M - tb)) * nvec < 2048) --tb;
+    int nt_pref = 512;
     if (tune && tune->tile_bits > 0) {
         // at most 64 KiB of LDS per tile
-        const int lim = ((dtype == SYK_C128) ? 12 : 13) - P.log_cw;
+        const int lim = (dtype == SYK_C128) ? 12 : 13;
         tb = std::max(0, std::min(std::min(tune->tile_bits, M), lim));
     }
-    if (tune && tune->threads > 0) nt_pref = P.single ? tune->threads : std::min(256, tune->threads);
+    if (tune && tune->threads > 0) nt_pref = tune->threads;
     P.tile_bits = tb;
-    const int elems = 1 << (tb + P.log_cw);
-    const int max_rpt = P.single ? 8 : 16;
+    const int elems = 1 << tb;
+    // up to 8 rows per thread with <= 256 threads, 4 rows beyond
+    auto rpt_cap = [](int nt) { return nt > 256 ? 4 : 8; };
     P.nt = std::min(nt_pref, elems);
-    // single kernel: up to 8 rows per thread with <= 256 threads, 4 rows beyond
-    const int max_nt = P.single ? 1024 : 256;
-    auto rpt_cap = [&](int nt) { return (P.single && nt > 256) ? 4 : max_rpt; };
-    while (elems / P.nt > rpt_cap(P.nt) && P.nt < max_nt) P.nt *= 2;
+    while (elems / P.nt > rpt_cap(P.nt) && P.nt < 1024) P.nt *= 2;
     P.rpt = elems / P.nt;
     if (P.rpt > rpt_cap(P.nt) || P.rpt * P.nt != elems)
         throw Error(SYK_EINVAL, "apply_H: tile does not fit the launch shape");
@@ -556,32 +411,31 @@ void launch_apply_h(const HamiltonianDev& H, syk_dtype dtype, int nvec, const in
                     const void* psi, void* out, const ApplyPlan& P, hipStream_t s)
 {
     const int M = H.M;
-    const Group* groups = H.groups_for(P.tile_bits, P.single);
-    const int n_groups = H.n_groups_for(P.tile_bits, P.single);
-    const FarRec* far = P.single ? H.far_for(P.tile_bits) : nullptr;
-    const int n_far = P.single ? H.n_far_for(P.tile_bits) : 0;
-    const int cw = 1 << P.log_cw;
-    const KRec* krec = P.single ? krecs_for(H, P) : nullptr;
+    const Group* groups = H.groups_for(P.tile_bits, true);
+    const int n_groups = H.n_groups_for(P.tile_bits, true);
+    const FarRec* far = H.far_for(P.tile_bits);
+    const int n_far = H.n_far_for(P.tile_bits);
+    const KRec* krec = krecs_for(H, P);
     timing_begin(s);
     for (int sl = 0; sl < P.slices; ++sl) {
         KLayout L{};
-        L.tile_bits = P.tile_bits;
-        L.log_cw = P.log_cw;
-        L.ld = nvec;
-        L.col0 = sl * cw;
-        L.n_tiles = (uint32_t)(((uint64_t)1 << M) >> P.tile_bits);
-        L.xcd_remap = P.xcd_remap;
         L.far = far;
         L.n_far = n_far;
-        for (int c = 0; c < cw; ++c) L.real[c] = real_of_col ? real_of_col[L.col0 + c] : 0;
+        L.tile_bits = P.tile_bits;
+        L.dim = (uint64_t)1 << M;
+        L.col0 = sl * kColsPerLaunch;
+        L.n_tiles = (uint32_t)(((uint64_t)1 << M) >> P.tile_bits);
+        L.xcd_remap = P.xcd_remap;
+        const int ncols = std::min(kColsPerLaunch, nvec - L.col0);
+        for (int c = 0; c < ncols; ++c) L.real[c] = real_of_col ? real_of_col[L.col0 + c] : 0;
         if (dtype == SYK_C128) {
             KTerms<double> T{H.masks, groups, H.tab4_d, H.qinfo, H.phi2_d, H.w2_d, H.dz, H.dw_d,
                              n_groups, H.n_diag, H.n_real, M};
-            launch_t<double>(P, T, krec, L, psi, out, s);
+            launch_t<double>(P, T, krec, L, ncols, psi, out, s);
         } else {
             KTerms<float> T{H.masks, groups, H.tab4_f, H.qinfo, H.phi2_f, H.w2_f, H.dz, H.dw_f,
                             n_groups, H.n_diag, H.n_real, M};
-            launch_t<float>(P, T, krec, L, psi, out, s);
+            launch_t<float>(P, T, krec, L, ncols, psi, out, s);
         }
     }
     timing_end(s);

@@ -32,14 +32,14 @@ struct ApplyTuning {
     int xcd_remap;
 };
 
+constexpr int kColsPerLaunch = 64;   // columns of a block served by one launch
+
 struct ApplyPlan {
     int tile_bits;   // rows per workgroup tile = 2^tile_bits
-    int log_cw;      // interleaved columns per tile = 2^log_cw
-    int slices;      // launches over column slices (nvec / 2^log_cw)
+    int slices;      // launches over column slices of kColsPerLaunch
     int nt;          // threads per workgroup
-    int rpt;         // tile elements per thread
+    int rpt;         // tile rows per thread
     int xcd_remap;
-    bool single;     // one column: the specialised single-vector kernel
 };
 
 ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune);
@@ -55,7 +55,7 @@ struct ApplyPlan;
 // Device mask records for a single-vector launch shape (built on first use).
 const KRec* krecs_for(const HamiltonianDev& H, const ApplyPlan& P);
 
-// out = H psi for a [dim][nvec] block; real_of_col: host array or NULL.
+// out = H psi for nvec columns stored one after another; real_of_col: host array or NULL.
 void launch_apply_h(const HamiltonianDev& H, syk_dtype dtype, int nvec, const int32_t* real_of_col,
                     const void* psi, void* out, const ApplyPlan& P, hipStream_t s);
 

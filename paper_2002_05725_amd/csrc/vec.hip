@@ -1,11 +1,11 @@
-// Vector kernels on [dim][nvec] blocks (row-major, entry (r, c) at r*nvec + c).
+// Vector kernels on blocks of nvec states of dimension dim, stored one after
+// another (entry (r, c) at c*dim + r).
 //
-// Every kernel uses the same thread layout: a 256-thread workgroup covers cb
-// columns (cb = next power of two >= min(nvec, 256)) times 256/cb rows, and
-// strides over rows, so each thread keeps one column and consecutive threads
-// touch consecutive addresses.  Reductions accumulate in FP64 per thread, then
-// reduce over the workgroup with a fixed-shape tree in LDS, then over the fixed
-// number of workgroups in index order: the result does not depend on timing.
+// Grid (gx, nvec): workgroup (bx, c) strides over the rows of column c, so
+// loads are coalesced and every column reduces on its own.  Reductions
+// accumulate in FP64 per thread, reduce over the workgroup with a fixed-shape
+// tree in LDS, then over the fixed number of workgroups in index order: the
+// result does not depend on timing.
 #include <cmath>
 #include <cstring>
 
@@ -16,60 +16,30 @@ namespace syk {
 namespace {
 
 constexpr int RB = 256;    // threads per workgroup
-constexpr int RG = 480;    // workgroups of a reduction (fixed for reproducibility)
+constexpr int RG = 240;    // workgroups per column of a reduction (fixed for reproducibility)
 constexpr int KC = 8;      // vectors per pass of a multi-vector kernel
 
 struct Shape {
-    int64_t D;
-    int B;
-    int log_cb;
-    int log_nrl;
+    int64_t D;   // rows per column
+    int B;       // columns
 };
-
-inline Shape make_shape(int64_t D, int B)
-{
-    int cb = 1;
-    while (cb < B && cb < RB) cb <<= 1;
-    int lc = 0;
-    while ((1 << lc) < cb) ++lc;
-    return {D, B, lc, 8 - lc};
-}
 
 inline dim3 grid_of(const Shape& S, bool reduction)
 {
-    const int cb = 1 << S.log_cb, nrl = 1 << S.log_nrl;
-    int64_t want = (S.D + nrl - 1) / nrl;
-    int gx = reduction ? RG : 4096;
+    int64_t want = (S.D + RB - 1) / RB;
+    int gx = reduction ? RG : std::max<int64_t>(1, 4096 / std::max(1, S.B));
     if (want < gx) gx = (int)want;
     if (gx < 1) gx = 1;
-    return dim3(gx, (S.B + cb - 1) / cb);
+    return dim3(gx, S.B);
 }
 
-struct Lane {
-    int col, rl;
-    bool valid;
-};
-
-__device__ __forceinline__ Lane lane_of(const Shape& S)
+// Sum red[i][*] over the workgroup (fixed tree); thread 0 holds the totals.
+__device__ __forceinline__ void tree_reduce(double* red, int n)
 {
-    Lane l;
-    const int cl = threadIdx.x & ((1 << S.log_cb) - 1);
-    l.rl = threadIdx.x >> S.log_cb;
-    l.col = blockIdx.y * (1 << S.log_cb) + cl;
-    l.valid = l.col < S.B;
-    return l;
-}
-
-// Sum v over the workgroup's row lanes of each column (fixed tree); lanes
-// with rl == 0 receive their column's total.
-__device__ __forceinline__ void tree_reduce(double* red, int n, const Shape& S)
-{
-    // red: [n][RB] doubles, already written by every thread at [i][threadIdx.x]
     __syncthreads();
-    const int rl = threadIdx.x >> S.log_cb;
-    for (int s = (1 << S.log_nrl) >> 1; s > 0; s >>= 1) {
-        if (rl < s)
-            for (int i = 0; i < n; ++i) red[i * RB + threadIdx.x] += red[i * RB + threadIdx.x + (s << S.log_cb)];
+    for (int s = RB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int i = 0; i < n; ++i) red[i * RB + threadIdx.x] += red[i * RB + threadIdx.x + s];
         __syncthreads();
     }
 }
@@ -78,16 +48,15 @@ template <typename R>
 __global__ void __launch_bounds__(RB) k_majorana(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                                  Shape S, int a)
 {
-    const Lane l = lane_of(S);
-    if (!l.valid) return;
+    const int64_t col = (int64_t)blockIdx.y * S.D;
     const int k = a >> 1;
     const uint64_t bit = (uint64_t)1 << k;
     const uint64_t below = bit - 1;
     const R amp = (R)0.70710678118654752440;
-    const int64_t step = (int64_t)gridDim.x << S.log_nrl;
-    for (int64_t r = ((int64_t)blockIdx.x << S.log_nrl) + l.rl; r < S.D; r += step) {
+    const int64_t step = (int64_t)gridDim.x * RB;
+    for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < S.D; r += step) {
         const uint64_t s = (uint64_t)r ^ bit;   // source row
-        const cplx<R> v = in[s * S.B + l.col];
+        const cplx<R> v = in[col + (int64_t)s];
         int neg = __popcll(s & below) & 1;
         cplx<R> o;
         if (a & 1) {             // i (-1)^{s_k} times the Z string
@@ -99,94 +68,91 @@ __global__ void __launch_bounds__(RB) k_majorana(const cplx<R>* __restrict__ in,
             o.im = amp * v.im;
         }
         if (neg) { o.re = -o.re; o.im = -o.im; }
-        out[(uint64_t)r * S.B + l.col] = o;
+        out[col + r] = o;
     }
 }
 
-// partial[blk][k][c] = sum over this workgroup's rows of conj(V_k[r,c]) w[r,c]
+// partial[bx][k][c] = sum over this workgroup's rows of conj(V_k[r,c]) w[r,c]
 template <typename R>
 __global__ void __launch_bounds__(RB) k_multidot(const cplx<R>* __restrict__ V, int64_t vstride, int K,
                                                  const cplx<R>* __restrict__ w, Shape S,
                                                  double* __restrict__ partial)
 {
     __shared__ double red[2 * KC * RB];
-    const Lane l = lane_of(S);
+    const int64_t col = (int64_t)blockIdx.y * S.D;
     double ar[KC], ai[KC];
 #pragma unroll
     for (int k = 0; k < KC; ++k) ar[k] = ai[k] = 0.0;
-    if (l.valid) {
-        const int64_t step = (int64_t)gridDim.x << S.log_nrl;
-        for (int64_t r = ((int64_t)blockIdx.x << S.log_nrl) + l.rl; r < S.D; r += step) {
-            const int64_t e = r * S.B + l.col;
-            const cplx<R> b = w[e];
-            const double br = b.re, bi = b.im;
+    const int64_t step = (int64_t)gridDim.x * RB;
+    for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < S.D; r += step) {
+        const int64_t e = col + r;
+        const cplx<R> b = w[e];
+        const double br = b.re, bi = b.im;
 #pragma unroll
-            for (int k = 0; k < KC; ++k)
-                if (k < K) {
-                    const cplx<R> v = V[k * vstride + e];
-                    const double vr = v.re, vi = v.im;
-                    ar[k] += vr * br + vi * bi;
-                    ai[k] += vr * bi - vi * br;
-                }
-        }
+        for (int k = 0; k < KC; ++k)
+            if (k < K) {
+                const cplx<R> v = V[k * vstride + e];
+                const double vr = v.re, vi = v.im;
+                ar[k] += vr * br + vi * bi;
+                ai[k] += vr * bi - vi * br;
+            }
     }
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
         red[(2 * k) * RB + threadIdx.x] = ar[k];
         red[(2 * k + 1) * RB + threadIdx.x] = ai[k];
     }
-    tree_reduce(red, 2 * K, S);
-    if (l.valid && l.rl == 0)
+    tree_reduce(red, 2 * K);
+    if (threadIdx.x == 0)
         for (int k = 0; k < K; ++k) {
-            double* p = partial + (((int64_t)blockIdx.x * K + k) * S.B + l.col) * 2;
-            p[0] = red[(2 * k) * RB + threadIdx.x];
-            p[1] = red[(2 * k + 1) * RB + threadIdx.x];
+            double* p = partial + (((int64_t)blockIdx.x * K + k) * S.B + blockIdx.y) * 2;
+            p[0] = red[(2 * k) * RB];
+            p[1] = red[(2 * k + 1) * RB];
         }
 }
 
-// w -= sum_k coef[k][c] V_k; optionally partial[blk][c] = sum |w_new|^2
+// w -= sum_k coef[k][c] V_k; optionally partial[bx][c] = sum |w_new|^2
 template <typename R>
 __global__ void __launch_bounds__(RB) k_update(cplx<R>* __restrict__ w, const cplx<R>* __restrict__ V,
                                                int64_t vstride, int K, const double* __restrict__ coef,
                                                Shape S, double* __restrict__ partial)
 {
     __shared__ double red[RB];
-    const Lane l = lane_of(S);
+    const int c = blockIdx.y;
+    const int64_t col = (int64_t)c * S.D;
     double cr[KC], ci[KC];
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-        cr[k] = (l.valid && k < K) ? coef[(k * S.B + l.col) * 2] : 0.0;
-        ci[k] = (l.valid && k < K) ? coef[(k * S.B + l.col) * 2 + 1] : 0.0;
+        cr[k] = (k < K) ? coef[(k * S.B + c) * 2] : 0.0;
+        ci[k] = (k < K) ? coef[(k * S.B + c) * 2 + 1] : 0.0;
     }
     double nrm = 0.0;
-    if (l.valid) {
-        const int64_t step = (int64_t)gridDim.x << S.log_nrl;
-        for (int64_t r = ((int64_t)blockIdx.x << S.log_nrl) + l.rl; r < S.D; r += step) {
-            const int64_t e = r * S.B + l.col;
-            const cplx<R> b = w[e];
-            double xr = b.re, xi = b.im;
+    const int64_t step = (int64_t)gridDim.x * RB;
+    for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < S.D; r += step) {
+        const int64_t e = col + r;
+        const cplx<R> b = w[e];
+        double xr = b.re, xi = b.im;
 #pragma unroll
-            for (int k = 0; k < KC; ++k)
-                if (k < K) {
-                    const cplx<R> v = V[k * vstride + e];
-                    xr -= cr[k] * v.re - ci[k] * v.im;
-                    xi -= cr[k] * v.im + ci[k] * v.re;
-                }
-            cplx<R> o;
-            o.re = (R)xr;
-            o.im = (R)xi;
-            w[e] = o;
-            const double orr = o.re, oi = o.im;
-            nrm += orr * orr + oi * oi;
-        }
+        for (int k = 0; k < KC; ++k)
+            if (k < K) {
+                const cplx<R> v = V[k * vstride + e];
+                xr -= cr[k] * v.re - ci[k] * v.im;
+                xi -= cr[k] * v.im + ci[k] * v.re;
+            }
+        cplx<R> o;
+        o.re = (R)xr;
+        o.im = (R)xi;
+        w[e] = o;
+        const double orr = o.re, oi = o.im;
+        nrm += orr * orr + oi * oi;
     }
     if (!partial) return;
     red[threadIdx.x] = nrm;
-    tree_reduce(red, 1, S);
-    if (l.valid && l.rl == 0) partial[(int64_t)blockIdx.x * S.B + l.col] = red[threadIdx.x];
+    tree_reduce(red, 1);
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * S.B + c] = red[0];
 }
 
-// Sum partial[g][i] over g < G in index order, for i < n (re/im as separate doubles: n counts doubles).
+// Sum partial[g][i] over g < G in index order, for i < n doubles.
 __global__ void k_finish(const double* __restrict__ partial, int G, int n, double* __restrict__ out)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -199,12 +165,11 @@ __global__ void k_finish(const double* __restrict__ partial, int G, int n, doubl
 template <typename R>
 __global__ void __launch_bounds__(RB) k_scale(cplx<R>* out, const cplx<R>* in, const double* __restrict__ f, Shape S)
 {
-    const Lane l = lane_of(S);
-    if (!l.valid) return;
-    const double fc = f[l.col];
-    const int64_t step = (int64_t)gridDim.x << S.log_nrl;
-    for (int64_t r = ((int64_t)blockIdx.x << S.log_nrl) + l.rl; r < S.D; r += step) {
-        const int64_t e = r * S.B + l.col;
+    const int64_t col = (int64_t)blockIdx.y * S.D;
+    const double fc = f[blockIdx.y];
+    const int64_t step = (int64_t)gridDim.x * RB;
+    for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < S.D; r += step) {
+        const int64_t e = col + r;
         const cplx<R> v = in[e];
         cplx<R> o;
         o.re = (R)(fc * (double)v.re);
@@ -218,14 +183,14 @@ template <typename R>
 __global__ void __launch_bounds__(RB) k_combine(cplx<R>* __restrict__ y, const cplx<R>* __restrict__ V,
                                                 int64_t vstride, int K, const double* __restrict__ coef, Shape S)
 {
-    const Lane l = lane_of(S);
-    if (!l.valid) return;
-    const int64_t step = (int64_t)gridDim.x << S.log_nrl;
-    for (int64_t r = ((int64_t)blockIdx.x << S.log_nrl) + l.rl; r < S.D; r += step) {
-        const int64_t e = r * S.B + l.col;
+    const int c = blockIdx.y;
+    const int64_t col = (int64_t)c * S.D;
+    const int64_t step = (int64_t)gridDim.x * RB;
+    for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < S.D; r += step) {
+        const int64_t e = col + r;
         double xr = 0.0, xi = 0.0;
         for (int k = 0; k < K; ++k) {
-            const double cr = coef[(k * S.B + l.col) * 2], ci = coef[(k * S.B + l.col) * 2 + 1];
+            const double cr = coef[(k * S.B + c) * 2], ci = coef[(k * S.B + c) * 2 + 1];
             const cplx<R> v = V[k * vstride + e];
             xr += cr * v.re - ci * v.im;
             xi += cr * v.im + ci * v.re;
@@ -242,6 +207,7 @@ __global__ void __launch_bounds__(RB) k_combine(cplx<R>* __restrict__ y, const c
 VecOps::VecOps(syk_terms_s& h, syk_dtype dt, int64_t dim, int nvec, hipStream_t s)
     : h_(h), dt_(dt), dim_(dim), nvec_(nvec), s_(s)
 {
+    require(nvec >= 1 && nvec <= 65535, "nvec must be in [1, 65535]");
 }
 
 void* VecOps::upload(const std::vector<zd>& c)
@@ -273,7 +239,7 @@ std::vector<T> VecOps::download(const void* dev, size_t n)
 
 void VecOps::majorana(int a, const void* in, void* out)
 {
-    Shape S = make_shape(dim_, nvec_);
+    Shape S{dim_, nvec_};
     dim3 g = grid_of(S, false);
     if (dt_ == SYK_C128)
         hipLaunchKernelGGL(k_majorana<double>, g, dim3(RB), 0, s_, (const c128*)in, (c128*)out, S, a);
@@ -284,7 +250,7 @@ void VecOps::majorana(int a, const void* in, void* out)
 
 std::vector<zd> VecOps::multidot(const void* V, int K, const void* w)
 {
-    Shape S = make_shape(dim_, nvec_);
+    Shape S{dim_, nvec_};
     dim3 g = grid_of(S, true);
     const int B = nvec_;
     std::vector<zd> res((size_t)K * B);
@@ -320,7 +286,7 @@ std::vector<double> VecOps::norm2(const void* a)
 
 std::vector<double> VecOps::update(void* w, const void* V, int K, const std::vector<zd>& coef, bool want_norm)
 {
-    Shape S = make_shape(dim_, nvec_);
+    Shape S{dim_, nvec_};
     const int B = nvec_;
     dim3 g = grid_of(S, true);
     std::vector<double> norms;
@@ -348,7 +314,7 @@ std::vector<double> VecOps::update(void* w, const void* V, int K, const std::vec
 
 void VecOps::scale(void* out, const void* in, const std::vector<double>& f)
 {
-    Shape S = make_shape(dim_, nvec_);
+    Shape S{dim_, nvec_};
     dim3 g = grid_of(S, false);
     double* df = (double*)upload(f);
     if (dt_ == SYK_C128)
@@ -360,7 +326,7 @@ void VecOps::scale(void* out, const void* in, const std::vector<double>& f)
 
 void VecOps::combine(void* y, const void* V, int K, const std::vector<zd>& coef)
 {
-    Shape S = make_shape(dim_, nvec_);
+    Shape S{dim_, nvec_};
     dim3 g = grid_of(S, false);
     double* dcoef = (double*)upload(coef);
     if (dt_ == SYK_C128)
