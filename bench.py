@@ -81,6 +81,54 @@ def timed_leg(api, torch, T, psi, steps, warmup, m, dt):
     return t1 - t0, n_apply, apply_ms
 
 
+def batched_leg(api, inputs, torch, np, dev, N, m, dt):
+    """Disorder-averaging block: 32 realisations x 2 typical states at N, one
+    Lanczos step of the 64-column complex64 block, against one step of a
+    single complex128 vector (the plain path) on the same GPU."""
+    R = 32
+    Js = np.stack([inputs.couplings(N, inputs.batch_coupling_seed(N, r)) for r in range(R)])
+    T = api.Terms(N, Js)
+    real = np.repeat(np.arange(R), 2)
+    host = np.stack([inputs.typical_state(N, inputs.batch_state_seed(N, r, s)) for r in range(R) for s in range(2)])
+    blk = torch.from_numpy(host).to(dev).to(torch.complex64)
+    one = torch.from_numpy(host[0]).to(dev)
+    del host
+    out = {"N": N, "columns": 64, "realisations": R, "m": m, "dt": dt}
+    for name, x, rc, cols in (("block_c64", blk, real, 64), ("single_c128", one, None, 1)):
+        api.krylov_expmv(T, x, -1j, dt, m=m, dt=dt, real_of_col=rc)      # warmup
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.krylov_expmv(T, x, -1j, dt, m=m, dt=dt, real_of_col=rc)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[name] = {"ms_per_step": t * 1e3, "vector_steps_per_s": cols / t}
+    out["speedup_per_vector"] = out["block_c64"]["vector_steps_per_s"] / out["single_c128"]["vector_steps_per_s"]
+    T.close()
+    return out
+
+
+def grad_leg(api, inputs, torch, dev, N, t_star, degree, dt, beta):
+    """Cost of dF/dJ for every coupling against the Chebyshev forward alone."""
+    J = inputs.couplings(N, 0)
+    T = api.Terms(N, J)
+    psi = torch.from_numpy(inputs.typical_state(N, 1)).to(dev)
+    lo, hi = api.spectrum_bounds(T, psi, 60)
+    o = api.cheb_opts(degree=degree, dt=dt, tau_steps=1, checkpoint_every=10, e_halfwidth=1.1 * max(abs(lo), abs(hi)))
+    api.cheb_otoc(T, 0, 1, beta, t_star, psi, o)            # warmup
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = api.cheb_otoc(T, 0, 1, beta, t_star, psi, o)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    F2, g = api.grad_couplings(T, 0, 1, beta, t_star, psi, o)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    T.close()
+    return {"N": N, "t_star": t_star, "degree": degree, "dt": dt, "beta": beta, "n_couplings": int(g.size),
+            "forward_s": tf, "grad_s": tg, "grad_fwd_ratio": tg / tf, "F": F, "F_from_grad_call": F2}
+
+
 def cpu_baseline(N, J, psi_host, m, target_s):
     """The CPU checker's term-by-term apply on a contiguous block of rows,
     scaled to one full apply, times m applications per time step."""
@@ -116,6 +164,8 @@ def main():
     ap.add_argument("--c64-steps", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-N", type=int, default=40, help="size of the batched leg (0: skip)")
+    ap.add_argument("--grad-N", type=int, default=36, help="size of the gradient leg (0: skip)")
     ap.add_argument("--profile-apply", type=int, default=0,
                     help="only run this many complex128 apply_H calls and one 1 GiB device copy "
                          "(for hardware-counter runs), then exit")
@@ -185,6 +235,19 @@ def main():
         del p64
         log(f"[bench] c64: {c64['ms_per_step']:.0f} ms/step, apply {a64 * 1e3:.1f} ms")
 
+    batched = None
+    if args.batch_N > 0:
+        torch.cuda.empty_cache()
+        log(f"[bench] batched leg: N={args.batch_N}, 32 realisations x 2 states")
+        batched = batched_leg(api, inputs, torch, np, dev, args.batch_N, 16, 0.5)
+        log(f"[bench] batched: {batched['speedup_per_vector']:.2f}x per vector vs single complex128")
+    grad = None
+    if args.grad_N > 0:
+        torch.cuda.empty_cache()
+        log(f"[bench] gradient leg: N={args.grad_N}")
+        grad = grad_leg(api, inputs, torch, dev, args.grad_N, 1.0, 32, 0.1, 5.0)
+        log(f"[bench] grad/fwd = {grad['grad_fwd_ratio']:.2f}")
+
     traffic = traffic_from_profile(f"N{N}_c128")
     out = {
         "metric": METRIC,
@@ -223,6 +286,9 @@ def main():
             "traffic_unit": "bytes per apply (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },
         "complex64": c64,
+        "batched": batched,
+        "gradient": grad,
+        "grad_fwd_ratio": grad["grad_fwd_ratio"] if grad else None,
     }
     if not args.no_cpu_baseline:
         log("[bench] CPU checker baseline")
