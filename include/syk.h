@@ -91,11 +91,12 @@ syk_status syk_apply_H(syk_terms t, syk_dtype dtype, int nvec, const int32_t* re
                        const void* psi, void* out, hipStream_t stream);
 
 /* Launch shape of apply_H for this handle (used by the autotuner): each
- * workgroup owns 2^tile_bits rows (0 = automatic), with `threads` threads
- * (0 = automatic, else a power of two in [64, 1024]; blocks of several columns
- * use at most 256); xcd_remap = 1 hands each of the 8 XCDs
- * a contiguous range of row tiles, 0 keeps the hardware's round-robin order.
- * Shapes that cannot launch give SYK_EINVAL and leave the setting unchanged. */
+ * workgroup owns 2^tile_bits rows (0 = automatic, else at most 11; capped at
+ * the number of qubits) with min(256, 2^tile_bits) threads, each thread up to 8
+ * rows.  threads: 0 or 256 (accepted for compatibility; the thread count
+ * follows from tile_bits).  xcd_remap = 1 hands each of the 8 XCDs a
+ * contiguous range of row tiles, 0 keeps the hardware's round-robin order.
+ * Other values give SYK_EINVAL and leave the setting unchanged. */
 syk_status syk_set_apply_tuning(syk_terms t, int tile_bits, int threads, int xcd_remap);
 
 /* Kernel timing: while enabled, every apply_H call records a HIP event before

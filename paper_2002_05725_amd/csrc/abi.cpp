@@ -229,9 +229,8 @@ syk_status syk_set_apply_tuning(syk_terms t, int tile_bits, int threads, int xcd
 {
     return guard([&] {
         check_handle(t);
-        require(tile_bits >= 0 && tile_bits <= 30, "tile_bits must be in [0, 30]");
-        require(threads == 0 || threads == 64 || threads == 128 || threads == 256 || threads == 512 || threads == 1024,
-                "threads must be 0 or a power of two in [64, 1024]");
+        require(tile_bits >= 0 && tile_bits <= 11, "tile_bits must be in [0, 11]");
+        require(threads == 0 || threads == 256, "threads must be 0 or 256");
         require(xcd_remap == 0 || xcd_remap == 1, "xcd_remap must be 0 or 1");
         const bool o_tuned = t->tuned;
         const int o_tb = t->tune_tile_bits, o_nt = t->tune_threads, o_x = t->tune_xcd;

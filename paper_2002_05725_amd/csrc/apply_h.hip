@@ -13,6 +13,9 @@
 // realisation, so mask records, PAIR weights and DIAG terms are wave-uniform
 // (scalar loads) and the chunk's QUAD tables are staged into LDS next to the
 // source tile.  Up to 64 columns per launch.
+#include <algorithm>
+#include <utility>
+
 #include "apply_h.hpp"
 #include "timing.hpp"
 
@@ -22,21 +25,21 @@ namespace {
 
 template <typename R>
 struct KTerms {
-    const MaskRec* __restrict__ masks;
-    const Group* __restrict__ groups;
     const cplx<R>* __restrict__ tab4;
     const uint32_t* __restrict__ qinfo;
     const cplx<R>* __restrict__ phi2;
     const R* __restrict__ w2;
     const uint32_t* __restrict__ dz;
     const R* __restrict__ dw;
-    int n_groups, n_diag, n_real, M;
+    int n_diag, n_real, M;
 };
 
 struct KLayout {
     const FarRec* __restrict__ far;   // QUAD masks flipping only tile bits
     int n_far;
+    int n_chunks;
     int tile_bits;     // rows per tile = 2^tile_bits
+    int lane_bits;     // threads per workgroup = 2^lane_bits
     uint64_t dim;      // rows per column
     int col0;          // first column of this launch (column = col0 + blockIdx.y)
     uint32_t n_tiles;  // dim >> tile_bits
@@ -77,27 +80,81 @@ __device__ __forceinline__ uint32_t quad_index(uint32_t r, uint32_t qpack)
 
 namespace {
 
-// Thread layout of the single-vector kernel: row rl = tid + k * nt of the tile
-// (nt = 2^lane_bits threads, k < RPT).  A row index splits into lane bits
-// (tid, per lane), row bits (k, the same for every lane) and tile bits (base,
-// the same for the workgroup).  The tile bits of every QUAD table index and
-// sign are folded into the tables while they are staged; the row bits come
-// from the mask record; only the lane bits are computed per thread, once per
-// mask.
-template <typename R, int RPT>
-__global__ void __launch_bounds__(RPT >= 8 ? 256 : 1024) k_apply_single(KTerms<R> T, const KRec* __restrict__ krec, KLayout L,
-                                                       const cplx<R>* __restrict__ psi, cplx<R>* __restrict__ out)
-{
-    static_assert(RPT <= 12, "row info holds 12 rows");
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const uint32_t nt = blockDim.x;
-    const uint32_t tile_elems = nt * RPT;               // == 2^tile_bits
-    cplx<R>* src = reinterpret_cast<cplx<R>*>(smem_raw);
-    cplx<R>* tabs = src + tile_elems;                   // kChunkMasks x 16 entries
+// Thread layout: row rl = tid + (k << lb) of the tile (nt = 2^lb threads,
+// lb = 8 whenever a thread owns several rows, k < RPT).  A row index splits into
+// lane bits (tid), k bits (the same for every lane) and tile bits (the same for
+// the workgroup).
+//
+// QUAD masks: the tile bits of every table index and sign are folded into the
+// tables while they are staged.  Inside a chunk the host sorts the QUAD masks
+// by class: for each k bit, whether the mask flips it, has it in its Z string,
+// or neither.  Within a class the source offset of every row and the sign each
+// row adds are compile-time constants, and the rows use one table entry per
+// subset of the flipped k bits.  The lane part of the table index is a byte
+// gather of tid's bits (v_perm) and a dot product with the powers of two
+// (v_dot4), the lane part of the sign one popcount.
+constexpr int kLaneBits = 8;
 
+constexpr int class_bits(int cls, int kb, int digit)
+{
+    int r = 0;
+    for (int b = 0; b < kb; ++b) {
+        if (cls % 3 == digit) r |= 1 << b;
+        cls /= 3;
+    }
+    return r;
+}
+
+constexpr int ipow3(int n) { return n == 0 ? 1 : 3 * ipow3(n - 1); }
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+
+template <typename F, int... I>
+__device__ __forceinline__ void for_each_class(F& f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+
+template <typename R, int RPT>
+struct ApplyLds {
+    cplx<R> src[RPT << kLaneBits];
+    cplx<R> tabs[kChunkMasks * 16];
+};
+
+// Sign flip by a word whose bit 31 is the sign to apply (other bits zero).
+__device__ __forceinline__ double flip31(double x, uint32_t s)
+{
+    return __hiloint2double(__double2hiint(x) ^ (int)s, __double2loint(x));
+}
+__device__ __forceinline__ float flip31(float x, uint32_t s) { return __int_as_float(__float_as_int(x) ^ (int)s); }
+
+template <typename R>
+__device__ __forceinline__ void cmac(R& pr, R& pi, R a, R b, const cplx<R>& v)
+{
+    pr = fma(a, v.re, pr);
+    pr = fma(-b, v.im, pr);
+    pi = fma(a, v.im, pi);
+    pi = fma(b, v.re, pi);
+}
+
+template <typename R, int RPT>
+__global__ void __launch_bounds__(256) k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
+                                               const QRec* __restrict__ rec, KLayout L,
+                                               const cplx<R>* __restrict__ psi, cplx<R>* __restrict__ out)
+{
+    constexpr int KB = ilog2c(RPT);
+    constexpr uint32_t esz = sizeof(cplx<R>);
+    // byte weights of the four gathered index bits: esz * 2^m
+    constexpr uint32_t kDotW = (esz) | (2 * esz) << 8 | (4 * esz) << 16 | (8 * esz) << 24;
+    __shared__ ApplyLds<R, RPT> S;
+    const char* src_b = reinterpret_cast<const char*>(S.src);
+    const char* tab_b = reinterpret_cast<const char*>(S.tabs);
+    auto src_at = [&](uint32_t off) { return *reinterpret_cast<const cplx<R>*>(src_b + off); };
+    auto tab_at = [&](uint32_t off) { return *reinterpret_cast<const cplx<R>*>(tab_b + off); };
+
+    const uint32_t lb = (RPT > 1) ? (uint32_t)kLaneBits : (uint32_t)L.lane_bits;
+    const uint32_t nt = 1u << lb;
     const uint32_t tile = tile_of_block(blockIdx.x, L);
-    const uint32_t row_mask = (1u << L.tile_bits) - 1u;
-    const uint32_t kmask = row_mask & ~(nt - 1u);       // row bits that vary with k
+    const uint32_t kmask = (uint32_t)(RPT - 1) << lb;   // row bits that vary with k
     const uint32_t tid = threadIdx.x;
     const int rc = L.real[blockIdx.y];
     const int M = T.M;
@@ -105,134 +162,137 @@ __global__ void __launch_bounds__(RPT >= 8 ? 256 : 1024) k_apply_single(KTerms<R
     psi += (uint64_t)(L.col0 + blockIdx.y) * L.dim;   // this workgroup's column
     out += (uint64_t)(L.col0 + blockIdx.y) * L.dim;
 
+    // bits 0..3 and 4..7 of tid, one per byte
+    uint32_t B0 = 0, B1 = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        B0 |= ((tid >> i) & 1u) << (8 * i);
+        B1 |= ((tid >> (4 + i)) & 1u) << (8 * i);
+    }
+    const uint32_t tid_b = tid * esz;
+
     // complex128 sums directly in pr/pi; complex64 sums each chunk in FP32 and
     // carries the running total in FP64.
     constexpr bool kSplit = sizeof(R) < sizeof(double);
     double acc_re[RPT], acc_im[RPT];
     R pr[RPT], pi[RPT];
-    uint32_t roff[RPT];   // LDS byte offset of the thread's rows
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         acc_re[k] = acc_im[k] = 0.0;
         pr[k] = pi[k] = R(0);
-        roff[k] = (tid + k * nt) * (uint32_t)sizeof(cplx<R>);
     }
-    auto lds = [&](uint32_t byte_off) -> cplx<R> {
-        return *reinterpret_cast<const cplx<R>*>(smem_raw + byte_off);
-    };
 
-    for (int g = 0; g < T.n_groups; ++g) {
-        const Group G = T.groups[g];
+    for (int g = 0; g < L.n_chunks; ++g) {
+        const QApplyChunk C = chunks[g];
         __syncthreads();   // previous chunk is done with src / tabs
-        if (G.new_tile) {
-            const uint64_t sbase = (uint64_t)(tile ^ G.x_high) << L.tile_bits;
+        if (C.new_tile) {
+            const uint64_t sbase = (uint64_t)(tile ^ C.x_high) << L.tile_bits;
 #pragma unroll
-            for (int k = 0; k < RPT; ++k) src[tid + k * nt] = psi[sbase + tid + k * nt];
+            for (int k = 0; k < RPT; ++k) S.src[tid + k * nt] = psi[sbase + tid + k * nt];
         }
-        // Staged QUAD table entry i of mask j: sign_tile * T[i ^ index_tile].
-        for (uint32_t e = tid; e < G.n_quad * 16; e += nt) {
-            const uint32_t qt = G.quad_first + (e >> 4);
+        // Staged QUAD table entry i of slot j: sign_tile * T[i ^ index_tile].
+        for (uint32_t e = tid; e < C.n_quad * 16; e += nt) {
+            const uint32_t qt = rec[C.first + (e >> 4)].tab;
             const uint32_t qp = T.qinfo[2 * qt], zb = T.qinfo[2 * qt + 1];
             const cplx<R> c = T.tab4[((size_t)qt * T.n_real + rc) * 16 + ((e & 15u) ^ quad_index(base, qp))];
             const uint32_t sg = parity(base & zb);
             cplx<R> o;
             o.re = flip(c.re, sg);
             o.im = flip(c.im, sg);
-            tabs[e] = o;
+            S.tabs[e] = o;
         }
         __syncthreads();
 
-        for (uint32_t mi = G.first; mi < G.first + G.count; ++mi) {
-            const KRec m = krec[mi];
-            const uint32_t type = m.meta >> 28;
-            const uint32_t tab = m.meta & 0x03ffffffu;
-            const uint32_t xlb = m.xl * (uint32_t)sizeof(cplx<R>);
-            if (type == MASK_QUAD) {
-                const uint32_t path = (m.meta >> 26) & 3u;
-                const cplx<R>* tq = tabs + (tab - G.quad_first) * 16;
-                const uint32_t il = quad_index(tid, m.qpack);   // lane bits of the index
-                const uint32_t sl = parity(tid & m.zbase);      // lane bits of the sign
-                if (path != PATH_FULL) {
-                    const cplx<R> t = tq[il];
-                    const R tr = flip(t.re, sl), ti = flip(t.im, sl);
+        uint32_t mi = C.first;
+        auto quad_class = [&](auto cls) {
+            constexpr int CL = decltype(cls)::value;
+            constexpr uint32_t XK = (uint32_t)class_bits(CL, KB, 1);   // k bits the masks flip
+            constexpr uint32_t ZK = (uint32_t)class_bits(CL, KB, 2);   // k bits in their Z string
+            const uint32_t n = (C.cnt[CL >> 2] >> (8 * (CL & 3))) & 0xffu;
+            for (uint32_t i = 0; i < n; ++i, ++mi) {
+                const QRec q = rec[mi];
+                const uint32_t ia = __builtin_amdgcn_udot4(__builtin_amdgcn_perm(B1, B0, q.sel), kDotW,
+                                                           (mi - C.first) * 16u * esz, false);
+                const uint32_t sl = (uint32_t)__popc(tid & q.zl) << 31;
+                cplx<R> te[RPT];   // entry for the k bits in p = k & XK
 #pragma unroll
-                    for (int k = 0; k < RPT; ++k) {
-                        const uint32_t sk = (path == PATH_SIGN) ? (m.kinfo[k / 6] >> (5 * (k % 6) + 4)) & 1u : 0u;
-                        const R a = flip(tr, sk), b = flip(ti, sk);
-                        const cplx<R> v = lds(roff[k] ^ xlb);
-                        pr[k] = fma(a, v.re, pr[k]);
-                        pr[k] = fma(-b, v.im, pr[k]);
-                        pi[k] = fma(a, v.im, pi[k]);
-                        pi[k] = fma(b, v.re, pi[k]);
-                    }
-                } else {
+                for (int p = 0; p < RPT; ++p) {
+                    if ((p & ~(int)XK) != 0) continue;
+                    uint32_t off = 0;
 #pragma unroll
-                    for (int k = 0; k < RPT; ++k) {
-                        const uint32_t ki = (m.kinfo[k / 6] >> (5 * (k % 6))) & 31u;
-                        const cplx<R> t = tq[il | (ki & 15u)];
-                        const uint32_t s = sl ^ (ki >> 4);
-                        const R a = flip(t.re, s), b = flip(t.im, s);
-                        const cplx<R> v = lds(roff[k] ^ xlb);
-                        pr[k] = fma(a, v.re, pr[k]);
-                        pr[k] = fma(-b, v.im, pr[k]);
-                        pi[k] = fma(a, v.im, pi[k]);
-                        pi[k] = fma(b, v.re, pi[k]);
-                    }
+                    for (int b = 0; b < KB; ++b)
+                        if ((p >> b) & 1) off += (q.koffs >> (8 * b)) & 0xffu;
+                    const cplx<R> t = tab_at(ia + off);
+                    te[p].re = flip31(t.re, sl);
+                    te[p].im = flip31(t.im, sl);
                 }
-            } else if (type == MASK_PAIR) {
-                // D = (-1)^{|r & zbase|} sum_e phi_e (-1)^{s_q0 e_0 + s_q1 e_1} L_e(r),
-                // phi_e = Phi[idx = 3][e] (the entry with s_q0 = s_q1 = 0),
-                // L_e(r) = W_e + sum_c w_{e,c} r_c split into lane/tile bits (once)
-                // and row bits (per k).
-                const R* w = T.w2 + ((size_t)tab * T.n_real + rc) * 4 * (M + 1);
-                const cplx<R>* ph = T.phi2 + (size_t)tab * 16 + 12;
-                R l0 = w[M], l1 = w[(M + 1) + M], l2 = w[2 * (M + 1) + M], l3 = w[3 * (M + 1) + M];
-                for (int c = 0; c < M; ++c) {
-                    if ((1u << c) & kmask) continue;
-                    const R b = (R)bit(tid | base, c);
-                    l0 = fma(w[c], b, l0);
-                    l1 = fma(w[(M + 1) + c], b, l1);
-                    l2 = fma(w[2 * (M + 1) + c], b, l2);
-                    l3 = fma(w[3 * (M + 1) + c], b, l3);
-                }
-                const uint32_t sl = parity(tid & m.zbase);
-                const uint32_t q0 = mask_q(m.qpack, 0), q1 = mask_q(m.qpack, 1);
+                const uint32_t sb = tid_b ^ q.xoff;
 #pragma unroll
                 for (int k = 0; k < RPT; ++k) {
-                    const uint32_t ru = base | (k * nt);
-                    R k0 = l0, k1 = l1, k2 = l2, k3 = l3;
-                    for (uint32_t rb = ru & kmask; rb; rb &= rb - 1) {
-                        const int c = __ffs(rb) - 1;
-                        k0 += w[c];
-                        k1 += w[(M + 1) + c];
-                        k2 += w[2 * (M + 1) + c];
-                        k3 += w[3 * (M + 1) + c];
-                    }
-                    const uint32_t r = tid | ru;
-                    const uint32_t sa = bit(r, q0) ^ 1u, sb = bit(r, q1) ^ 1u;
-                    k1 = flip(k1, sa);
-                    k2 = flip(k2, sb);
-                    k3 = flip(k3, sa ^ sb);
-                    const uint32_t s = sl ^ parity(ru & m.zbase);
-                    const R dre = flip(ph[0].re * k0 + ph[1].re * k1 + ph[2].re * k2 + ph[3].re * k3, s);
-                    const R dim = flip(ph[0].im * k0 + ph[1].im * k1 + ph[2].im * k2 + ph[3].im * k3, s);
-                    const cplx<R> v = lds(roff[k] ^ xlb);
-                    pr[k] = fma(dre, v.re, pr[k]);
-                    pr[k] = fma(-dim, v.im, pr[k]);
-                    pi[k] = fma(dre, v.im, pi[k]);
-                    pi[k] = fma(dim, v.re, pi[k]);
+                    const cplx<R> t = te[k & (int)XK];
+                    const bool neg = (__builtin_popcount((uint32_t)k & ZK) & 1) != 0;
+                    const R a = neg ? -t.re : t.re, b = neg ? -t.im : t.im;
+                    const cplx<R> v = src_at(sb + (((uint32_t)k ^ XK) << kLaneBits) * esz);
+                    cmac(pr[k], pi[k], a, b, v);
                 }
-            } else {  // MASK_DIAG
-                const R* d = T.dw + (size_t)rc * T.n_diag;
+            }
+        };
+        for_each_class(quad_class, std::make_integer_sequence<int, ipow3(KB)>{});
+
+        // PAIR: D = (-1)^{|r & zbase|} sum_e phi_e (-1)^{s_q0 e_0 + s_q1 e_1} L_e(r),
+        // phi_e = Phi[idx = 3][e] (the entry with s_q0 = s_q1 = 0),
+        // L_e(r) = W_e + sum_c w_{e,c} r_c split into lane/tile bits (once)
+        // and k bits (per k).
+        for (uint32_t i = 0; i < C.n_pair; ++i, ++mi) {
+            const QRec q = rec[mi];
+            const R* w = T.w2 + ((size_t)q.tab * T.n_real + rc) * 4 * (M + 1);
+            const cplx<R>* ph = T.phi2 + (size_t)q.tab * 16 + 12;
+            R l0 = w[M], l1 = w[(M + 1) + M], l2 = w[2 * (M + 1) + M], l3 = w[3 * (M + 1) + M];
+            for (int c = 0; c < M; ++c) {
+                if ((1u << c) & kmask) continue;
+                const R b = (R)bit(tid | base, c);
+                l0 = fma(w[c], b, l0);
+                l1 = fma(w[(M + 1) + c], b, l1);
+                l2 = fma(w[2 * (M + 1) + c], b, l2);
+                l3 = fma(w[3 * (M + 1) + c], b, l3);
+            }
+            const uint32_t sl = parity(tid & q.zbase);
+            const uint32_t q0 = mask_q(q.qpack, 0), q1 = mask_q(q.qpack, 1);
+            const uint32_t sb = tid_b ^ q.xoff;
 #pragma unroll
-                for (int k = 0; k < RPT; ++k) {
-                    const uint32_t r = base | (tid + k * nt);
-                    const cplx<R> v = lds(roff[k] ^ xlb);
-                    R s = R(0);
-                    for (int n = 0; n < T.n_diag; ++n) s += flip(d[n], parity(r & T.dz[n]));
-                    pr[k] = fma(s, v.re, pr[k]);
-                    pi[k] = fma(s, v.im, pi[k]);
+            for (int k = 0; k < RPT; ++k) {
+                const uint32_t ru = base | ((uint32_t)k << lb);
+                R k0 = l0, k1 = l1, k2 = l2, k3 = l3;
+                for (uint32_t rb = ru & kmask; rb; rb &= rb - 1) {
+                    const int c = __ffs(rb) - 1;
+                    k0 += w[c];
+                    k1 += w[(M + 1) + c];
+                    k2 += w[2 * (M + 1) + c];
+                    k3 += w[3 * (M + 1) + c];
                 }
+                const uint32_t r = tid | ru;
+                const uint32_t sa = bit(r, q0) ^ 1u, sbb = bit(r, q1) ^ 1u;
+                k1 = flip(k1, sa);
+                k2 = flip(k2, sbb);
+                k3 = flip(k3, sa ^ sbb);
+                const uint32_t s = sl ^ parity(ru & q.zbase);
+                const R dre = flip(ph[0].re * k0 + ph[1].re * k1 + ph[2].re * k2 + ph[3].re * k3, s);
+                const R dim = flip(ph[0].im * k0 + ph[1].im * k1 + ph[2].im * k2 + ph[3].im * k3, s);
+                const cplx<R> v = src_at(sb + (((uint32_t)k ^ q.koffs) << lb) * esz);
+                cmac(pr[k], pi[k], dre, dim, v);
+            }
+        }
+        // DIAG (source = own row)
+        for (uint32_t i = 0; i < C.n_diag; ++i, ++mi) {
+            const R* d = T.dw + (size_t)rc * T.n_diag;
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) {
+                const uint32_t r = base | (tid + ((uint32_t)k << lb));
+                const cplx<R> v = src_at(tid_b + ((uint32_t)k << lb) * esz);
+                R s = R(0);
+                for (int n = 0; n < T.n_diag; ++n) s += flip(d[n], parity(r & T.dz[n]));
+                pr[k] = fma(s, v.re, pr[k]);
+                pi[k] = fma(s, v.im, pi[k]);
             }
         }
         if (kSplit) {
@@ -269,12 +329,7 @@ __global__ void __launch_bounds__(RPT >= 8 ? 256 : 1024) k_apply_single(KTerms<R
             const uint32_t s = parity(base & fc.zbase);
             const R tr = flip(t.re, s), ti = flip(t.im, s);
 #pragma unroll
-            for (int k = 0; k < RPT; ++k) {
-                pr[k] = fma(tr, v[k].re, pr[k]);
-                pr[k] = fma(-ti, v[k].im, pr[k]);
-                pi[k] = fma(tr, v[k].im, pi[k]);
-                pi[k] = fma(ti, v[k].re, pi[k]);
-            }
+            for (int k = 0; k < RPT; ++k) cmac(pr[k], pi[k], tr, ti, v[k]);
             if (kSplit && (f & 63) == 63) {
 #pragma unroll
                 for (int k = 0; k < RPT; ++k) {
@@ -310,21 +365,98 @@ inline int ilog2(int64_t v)
 }
 
 template <typename R>
-void launch_t(const ApplyPlan& P, const KTerms<R>& T, const KRec* krec, KLayout L, int ncols, const void* psi,
-              void* out, hipStream_t s)
+void launch_t(const ApplyPlan& P, const KTerms<R>& T, const QApplyChunk* chunks, const QRec* rec, KLayout L,
+              int ncols, const void* psi, void* out, hipStream_t s)
 {
     dim3 grid(L.n_tiles, ncols), block(P.nt);
-    const size_t lds = ((size_t)1 << P.tile_bits) * sizeof(cplx<R>) + (size_t)kChunkMasks * 16 * sizeof(cplx<R>);
     auto* in = static_cast<const cplx<R>*>(psi);
     auto* o = static_cast<cplx<R>*>(out);
     switch (P.rpt) {
-    case 1: hipLaunchKernelGGL((k_apply_single<R, 1>), grid, block, lds, s, T, krec, L, in, o); break;
-    case 2: hipLaunchKernelGGL((k_apply_single<R, 2>), grid, block, lds, s, T, krec, L, in, o); break;
-    case 4: hipLaunchKernelGGL((k_apply_single<R, 4>), grid, block, lds, s, T, krec, L, in, o); break;
-    case 8: hipLaunchKernelGGL((k_apply_single<R, 8>), grid, block, lds, s, T, krec, L, in, o); break;
+    case 1: hipLaunchKernelGGL((k_apply<R, 1>), grid, block, 0, s, T, chunks, rec, L, in, o); break;
+    case 2: hipLaunchKernelGGL((k_apply<R, 2>), grid, block, 0, s, T, chunks, rec, L, in, o); break;
+    case 4: hipLaunchKernelGGL((k_apply<R, 4>), grid, block, 0, s, T, chunks, rec, L, in, o); break;
+    case 8: hipLaunchKernelGGL((k_apply<R, 8>), grid, block, 0, s, T, chunks, rec, L, in, o); break;
     default: throw Error(SYK_EINVAL, "apply_H: unsupported rows per thread");
     }
     SYK_HIP(hipGetLastError());
+}
+
+// Chunks and class-sorted records of the apply kernel for tiles of 2^tile_bits
+// rows, 2^lane_bits threads and elements of esz bytes.  Masks are taken in x
+// order; QUAD masks whose flipped qubits are all tile bits are left to the far
+// list (make_groups with split_far).
+void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int lane_bits, uint32_t esz,
+                        std::vector<QApplyChunk>& chunks, std::vector<QRec>& recs)
+{
+    const uint32_t row_mask = (1u << tile_bits) - 1u;
+    const uint32_t lane_mask = (1u << lane_bits) - 1u;
+    const int kb = tile_bits - lane_bits;
+    if (kb < 0 || kb > kMaxKBits) throw Error(SYK_EINVAL, "apply_H: unsupported rows per thread");
+    const uint32_t kbits_mask = (1u << kb) - 1u;
+    auto quad_class = [&](const MaskRec& m) {
+        int cls = 0, p3 = 1;
+        for (int b = 0; b < kb; ++b, p3 *= 3) {
+            const uint32_t q = (uint32_t)(lane_bits + b);
+            if ((m.x >> q) & 1u) cls += p3;
+            else if ((m.zbase >> q) & 1u) cls += 2 * p3;
+        }
+        return cls;
+    };
+    auto type_of = [](const MaskRec& m) { return m.type_tab >> 28; };
+    size_t i = 0;
+    uint32_t prev_high = 0xffffffffu;
+    while (i < masks.size()) {
+        // masks of one chunk: same x_high, at most kChunkMasks
+        std::vector<uint32_t> mem;
+        const uint32_t xh = masks[i].x >> tile_bits;
+        while (i < masks.size() && (masks[i].x >> tile_bits) == xh && mem.size() < (size_t)kChunkMasks) {
+            const MaskRec& m = masks[i];
+            if (!(type_of(m) == MASK_QUAD && (m.x & row_mask) == 0u)) mem.push_back((uint32_t)i);
+            ++i;
+        }
+        if (mem.empty()) continue;
+        auto key = [&](uint32_t j) {
+            const MaskRec& m = masks[j];
+            const uint32_t t = type_of(m);
+            return t == MASK_QUAD ? quad_class(m) : t == MASK_PAIR ? 100 : 200;
+        };
+        std::stable_sort(mem.begin(), mem.end(), [&](uint32_t a, uint32_t b) { return key(a) < key(b); });
+        QApplyChunk c{};
+        c.x_high = xh;
+        c.first = (uint32_t)recs.size();
+        c.new_tile = (xh != prev_high) ? 1u : 0u;
+        prev_high = xh;
+        for (uint32_t j : mem) {
+            const MaskRec& m = masks[j];
+            const uint32_t t = type_of(m);
+            QRec r{};
+            r.zl = m.zbase & lane_mask;
+            r.xoff = (m.x & lane_mask) * esz;
+            r.tab = m.type_tab & 0x0fffffffu;
+            r.xl = m.x & row_mask;
+            r.qpack = m.qpack;
+            r.zbase = m.zbase;
+            if (t == MASK_QUAD) {
+                const int cls = quad_class(m);
+                ++c.n_quad;
+                c.cnt[cls >> 2] += 1u << (8 * (cls & 3));
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t qb = mask_q(m.qpack, q);
+                    r.sel |= (qb < (uint32_t)lane_bits ? qb : 0x0cu) << (8 * q);
+                    const int b = (int)qb - lane_bits;
+                    if (b >= 0 && b < kb) r.koffs |= ((1u << q) * esz) << (8 * b);
+                }
+            } else {
+                r.sel = 0x0c0c0c0cu;
+                r.koffs = (m.x >> lane_bits) & kbits_mask;
+                if (t == MASK_PAIR) ++c.n_pair;
+                else ++c.n_diag;
+            }
+            recs.push_back(r);
+        }
+        chunks.push_back(c);
+    }
+    recs.push_back(QRec{});   // one record past the end: loads may run one ahead
 }
 
 // Mask records for launch shape (tile_bits, nt), in mask order.
@@ -379,30 +511,49 @@ const KRec* krecs_for(const HamiltonianDev& H, const ApplyPlan& P)
     return it->second->as<KRec>();
 }
 
+namespace {
+
+const HamiltonianDev::ApplyTables& apply_tables_for(const HamiltonianDev& H, const ApplyPlan& P, uint32_t esz)
+{
+    const int key = (P.tile_bits * 16 + P.lb) * 32 + (int)esz;
+    auto it = H.apply_tables.find(key);
+    if (it == H.apply_tables.end()) {
+        std::vector<QApplyChunk> ch;
+        std::vector<QRec> rc;
+        build_apply_tables(*H.host_masks, P.tile_bits, P.lb, esz, ch, rc);
+        std::unique_ptr<HamiltonianDev::ApplyTables> t(new HamiltonianDev::ApplyTables());
+        t->n_chunks = (int)ch.size();
+        if (!ch.empty()) {
+            t->chunks.ensure(ch.size() * sizeof(QApplyChunk));
+            SYK_HIP(hipMemcpy(t->chunks.p, ch.data(), ch.size() * sizeof(QApplyChunk), hipMemcpyHostToDevice));
+        }
+        t->recs.ensure(rc.size() * sizeof(QRec));
+        SYK_HIP(hipMemcpy(t->recs.p, rc.data(), rc.size() * sizeof(QRec), hipMemcpyHostToDevice));
+        it = H.apply_tables.emplace(key, std::move(t)).first;
+    }
+    return *it->second;
+}
+
+}  // namespace
+
 ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune)
 {
+    (void)dtype;
     ApplyPlan P{};
     P.slices = (nvec + kColsPerLaunch - 1) / kColsPerLaunch;
-    // 2048-row source tiles with 512 threads (4 rows each): measured best at
-    // N=44 and N=52; smaller tiles when the columns would not fill the chip.
+    // 2048-row source tiles (256 threads, 8 rows each); smaller tiles when the
+    // columns would not fill the chip.
     int tb = std::min(M, 11);
     while (tb > 8 && ((int64_t)1 << (M - tb)) * nvec < 2048) --tb;
-    int nt_pref = 512;
-    if (tune && tune->tile_bits > 0) {
-        // at most 64 KiB of LDS per tile
-        const int lim = (dtype == SYK_C128) ? 12 : 13;
-        tb = std::max(0, std::min(std::min(tune->tile_bits, M), lim));
-    }
-    if (tune && tune->threads > 0) nt_pref = tune->threads;
+    if (tune && tune->tile_bits > 0) tb = std::min(tune->tile_bits, M);
+    // 8 lane bits; a thread owns 2^(tile_bits - 8) rows, at most 8
+    if (tb > kLaneBits + kMaxKBits) throw Error(SYK_EINVAL, "apply_H: tile_bits above 11");
     P.tile_bits = tb;
-    const int elems = 1 << tb;
-    // up to 8 rows per thread with <= 256 threads, 4 rows beyond
-    auto rpt_cap = [](int nt) { return nt > 256 ? 4 : 8; };
-    P.nt = std::min(nt_pref, elems);
-    while (elems / P.nt > rpt_cap(P.nt) && P.nt < 1024) P.nt *= 2;
-    P.rpt = elems / P.nt;
-    if (P.rpt > rpt_cap(P.nt) || P.rpt * P.nt != elems)
-        throw Error(SYK_EINVAL, "apply_H: tile does not fit the launch shape");
+    P.lb = std::min(tb, kLaneBits);
+    P.nt = 1 << P.lb;
+    P.rpt = 1 << (tb - P.lb);
+    if (tune && tune->threads != 0 && tune->threads != (1 << kLaneBits))
+        throw Error(SYK_EINVAL, "apply_H: threads must be 0 or 256");
     P.xcd_remap = tune ? tune->xcd_remap : 1;
     return P;
 }
@@ -411,31 +562,35 @@ void launch_apply_h(const HamiltonianDev& H, syk_dtype dtype, int nvec, const in
                     const void* psi, void* out, const ApplyPlan& P, hipStream_t s)
 {
     const int M = H.M;
-    const Group* groups = H.groups_for(P.tile_bits, true);
-    const int n_groups = H.n_groups_for(P.tile_bits, true);
+    if (P.lb > kLaneBits || (P.rpt > 1 && P.lb != kLaneBits) || P.nt != (1 << P.lb) ||
+        (P.rpt << P.lb) != (1 << P.tile_bits) || P.tile_bits > M)
+        throw Error(SYK_EINVAL, "apply_H: inconsistent launch shape");
+    (void)H.groups_for(P.tile_bits, true);   // builds the far list
     const FarRec* far = H.far_for(P.tile_bits);
     const int n_far = H.n_far_for(P.tile_bits);
-    const KRec* krec = krecs_for(H, P);
+    const HamiltonianDev::ApplyTables& A = apply_tables_for(H, P, (uint32_t)elem_bytes(dtype));
     timing_begin(s);
     for (int sl = 0; sl < P.slices; ++sl) {
         KLayout L{};
         L.far = far;
         L.n_far = n_far;
+        L.n_chunks = A.n_chunks;
         L.tile_bits = P.tile_bits;
+        L.lane_bits = P.lb;
         L.dim = (uint64_t)1 << M;
         L.col0 = sl * kColsPerLaunch;
         L.n_tiles = (uint32_t)(((uint64_t)1 << M) >> P.tile_bits);
         L.xcd_remap = P.xcd_remap;
         const int ncols = std::min(kColsPerLaunch, nvec - L.col0);
         for (int c = 0; c < ncols; ++c) L.real[c] = real_of_col ? real_of_col[L.col0 + c] : 0;
+        const auto* ch = A.chunks.as<QApplyChunk>();
+        const auto* rc = A.recs.as<QRec>();
         if (dtype == SYK_C128) {
-            KTerms<double> T{H.masks, groups, H.tab4_d, H.qinfo, H.phi2_d, H.w2_d, H.dz, H.dw_d,
-                             n_groups, H.n_diag, H.n_real, M};
-            launch_t<double>(P, T, krec, L, ncols, psi, out, s);
+            KTerms<double> T{H.tab4_d, H.qinfo, H.phi2_d, H.w2_d, H.dz, H.dw_d, H.n_diag, H.n_real, M};
+            launch_t<double>(P, T, ch, rc, L, ncols, psi, out, s);
         } else {
-            KTerms<float> T{H.masks, groups, H.tab4_f, H.qinfo, H.phi2_f, H.w2_f, H.dz, H.dw_f,
-                            n_groups, H.n_diag, H.n_real, M};
-            launch_t<float>(P, T, krec, L, ncols, psi, out, s);
+            KTerms<float> T{H.tab4_f, H.qinfo, H.phi2_f, H.w2_f, H.dz, H.dw_f, H.n_diag, H.n_real, M};
+            launch_t<float>(P, T, ch, rc, L, ncols, psi, out, s);
         }
     }
     timing_end(s);

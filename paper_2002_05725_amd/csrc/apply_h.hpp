@@ -25,6 +25,38 @@ enum : uint32_t {
     PATH_FULL = 2    // ... both depend on the row
 };
 
+// Mask record of the apply kernel for one launch shape and element size, in
+// the class-sorted order of its chunk (QApplyChunk).  The first four words are
+// what the QUAD loops read per mask; the rest serves table staging and the
+// PAIR / DIAG paths.
+struct alignas(16) QRec {
+    uint32_t sel;    // QUAD: byte selector gathering the lane bits of tid at q0..q3 (0x0c: not a lane bit)
+    uint32_t zl;     // lane bits of zbase
+    uint32_t xoff;   // (x & lane mask) * element size: lane part of the source offset
+    uint32_t koffs;  // QUAD: byte b = table byte offset of the index bit that k-bit b sets (0 if b is not flipped);
+                     // PAIR / DIAG: the k bits of x
+    uint32_t tab;    // index into the type's tables
+    uint32_t xl;     // x & (tile rows - 1)
+    uint32_t qpack;  // flipped qubits, one per byte
+    uint32_t zbase;  // Z string of the mask
+};
+static_assert(sizeof(QRec) == 32, "QRec layout");
+
+constexpr int kMaxKBits = 3;   // up to 8 rows per thread
+constexpr int kQuadClasses = 27;   // 3^kMaxKBits (k-bit flipped / in the Z string / neither)
+
+// One chunk of the apply kernel: masks sharing a source tile, QUAD masks first,
+// sorted by class, then PAIR, then DIAG.
+struct alignas(16) QApplyChunk {
+    uint32_t x_high;    // source tile = tile ^ x_high
+    uint32_t first;     // first record (index into the QRec array)
+    uint32_t new_tile;  // x_high differs from the previous chunk's
+    uint32_t n_quad;
+    uint32_t n_pair, n_diag, pad[2];
+    uint32_t cnt[8];    // QUAD masks per class, one byte per class
+};
+static_assert(sizeof(QApplyChunk) == 64, "QApplyChunk layout");
+
 // Optional overrides of the launch shape (autotuner / benchmarks); 0 = default.
 struct ApplyTuning {
     int tile_bits;
@@ -38,6 +70,7 @@ struct ApplyPlan {
     int tile_bits;   // rows per workgroup tile = 2^tile_bits
     int slices;      // launches over column slices of kColsPerLaunch
     int nt;          // threads per workgroup
+    int lb;          // lane bits: nt = 2^lb
     int rpt;         // tile rows per thread
     int xcd_remap;
 };

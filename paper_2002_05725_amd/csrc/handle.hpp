@@ -36,8 +36,14 @@ struct HamiltonianDev {
     int n_far_for(int tile_bits) const;
     mutable std::map<int, std::unique_ptr<DevBuf>> fars;
     mutable std::map<int, int> n_fars;
-    // Per-launch-shape mask records of the single-vector kernel, built on first use.
+    // Per-launch-shape mask records of the gradient kernel, built on first use.
     mutable std::map<int, std::unique_ptr<DevBuf>> krecs;
+    // Per-launch-shape chunks and class-sorted records of the apply kernel.
+    struct ApplyTables {
+        DevBuf chunks, recs;
+        int n_chunks = 0;
+    };
+    mutable std::map<int, std::unique_ptr<ApplyTables>> apply_tables;
 };
 
 // Named device workspaces, grown on demand and kept until the handle dies.
