@@ -192,8 +192,8 @@ __global__ void __launch_bounds__(256) k_apply(KTerms<R> T, const QApplyChunk* _
         }
         // Staged QUAD table entry i of slot j: sign_tile * T[i ^ index_tile].
         for (uint32_t e = tid; e < C.n_quad * 16; e += nt) {
-            const uint32_t qt = rec[C.first + (e >> 4)].tab;
-            const uint32_t qp = T.qinfo[2 * qt], zb = T.qinfo[2 * qt + 1];
+            const QRec& qr = rec[C.first + (e >> 4)];
+            const uint32_t qt = qr.tab, qp = qr.qpack, zb = qr.zbase;   // in this layout's coordinates
             const cplx<R> c = T.tab4[((size_t)qt * T.n_real + rc) * 16 + ((e & 15u) ^ quad_index(base, qp))];
             const uint32_t sg = parity(base & zb);
             cplx<R> o;
@@ -364,6 +364,56 @@ inline int ilog2(int64_t v)
     return l;
 }
 
+// dst = transpose of src viewed as a [2^log_h] x [2^log_w] matrix (row-major),
+// column by column of a block: dst[c][lo << log_h | hi] (+)= src[c][hi << log_w | lo].
+// 32 x 32 tiles through LDS so that both sides are read and written along
+// contiguous rows.  With ADD, complex64 sums are formed in FP64 and rounded once.
+template <typename R, bool ADD>
+__global__ void __launch_bounds__(256) k_transpose(const cplx<R>* __restrict__ src, cplx<R>* __restrict__ dst,
+                                                   int log_h, int log_w, uint64_t dim)
+{
+    __shared__ cplx<R> t[32][33];
+    const uint32_t lw = (uint32_t)log_w - 5u;
+    const uint64_t bx = blockIdx.x & ((1u << lw) - 1u);   // tile column (lo / 32)
+    const uint64_t by = blockIdx.x >> lw;                 // tile row (hi / 32)
+    src += (uint64_t)blockIdx.y * dim;
+    dst += (uint64_t)blockIdx.y * dim;
+    const uint32_t tx = threadIdx.x & 31u, ty = threadIdx.x >> 5;
+#pragma unroll
+    for (uint32_t j = ty; j < 32; j += 8) t[j][tx] = src[((by * 32 + j) << log_w) | (bx * 32 + tx)];
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = ty; j < 32; j += 8) {
+        const uint64_t o = ((bx * 32 + j) << log_h) | (by * 32 + tx);
+        cplx<R> v = t[tx][j];
+        if (ADD) {
+            const cplx<R> d = dst[o];
+            v.re = (R)((double)v.re + (double)d.re);
+            v.im = (R)((double)v.im + (double)d.im);
+        }
+        dst[o] = v;
+    }
+}
+
+void launch_transpose(syk_dtype dtype, const void* src, void* dst, int log_h, int log_w, int ncols, uint64_t dim,
+                      bool add, hipStream_t s)
+{
+    if (log_h < 5 || log_w < 5 || log_h + log_w > 40) throw Error(SYK_EINVAL, "transpose: unsupported shape");
+    dim3 grid((uint32_t)((dim >> 10)), ncols), block(256);
+    if (dtype == SYK_C128) {
+        auto* i = static_cast<const c128*>(src);
+        auto* o = static_cast<c128*>(dst);
+        if (add) hipLaunchKernelGGL((k_transpose<double, true>), grid, block, 0, s, i, o, log_h, log_w, dim);
+        else hipLaunchKernelGGL((k_transpose<double, false>), grid, block, 0, s, i, o, log_h, log_w, dim);
+    } else {
+        auto* i = static_cast<const c64*>(src);
+        auto* o = static_cast<c64*>(dst);
+        if (add) hipLaunchKernelGGL((k_transpose<float, true>), grid, block, 0, s, i, o, log_h, log_w, dim);
+        else hipLaunchKernelGGL((k_transpose<float, false>), grid, block, 0, s, i, o, log_h, log_w, dim);
+    }
+    SYK_HIP(hipGetLastError());
+}
+
 template <typename R>
 void launch_t(const ApplyPlan& P, const KTerms<R>& T, const QApplyChunk* chunks, const QRec* rec, KLayout L,
               int ncols, const void* psi, void* out, hipStream_t s)
@@ -382,11 +432,10 @@ void launch_t(const ApplyPlan& P, const KTerms<R>& T, const QApplyChunk* chunks,
 }
 
 // Chunks and class-sorted records of the apply kernel for tiles of 2^tile_bits
-// rows, 2^lane_bits threads and elements of esz bytes.  Masks are taken in x
-// order; QUAD masks whose flipped qubits are all tile bits are left to the far
-// list (make_groups with split_far).
+// rows, 2^lane_bits threads and elements of esz bytes.  masks must be sorted by
+// x; QUAD masks that flip no row bit inside a tile go to the far list.
 void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int lane_bits, uint32_t esz,
-                        std::vector<QApplyChunk>& chunks, std::vector<QRec>& recs)
+                        std::vector<QApplyChunk>& chunks, std::vector<QRec>& recs, std::vector<FarRec>& far)
 {
     const uint32_t row_mask = (1u << tile_bits) - 1u;
     const uint32_t lane_mask = (1u << lane_bits) - 1u;
@@ -411,7 +460,10 @@ void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int la
         const uint32_t xh = masks[i].x >> tile_bits;
         while (i < masks.size() && (masks[i].x >> tile_bits) == xh && mem.size() < (size_t)kChunkMasks) {
             const MaskRec& m = masks[i];
-            if (!(type_of(m) == MASK_QUAD && (m.x & row_mask) == 0u)) mem.push_back((uint32_t)i);
+            if (type_of(m) == MASK_QUAD && (m.x & row_mask) == 0u)
+                far.push_back({m.x >> tile_bits, m.qpack, m.zbase, m.type_tab & 0x0fffffffu});
+            else
+                mem.push_back((uint32_t)i);
             ++i;
         }
         if (mem.empty()) continue;
@@ -457,6 +509,48 @@ void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int la
         chunks.push_back(c);
     }
     recs.push_back(QRec{});   // one record past the end: loads may run one ahead
+}
+
+// Bit rotation of the second layout: bits s..M-1 of a row become bits
+// 0..M-s-1 and bits 0..s-1 become the top bits.
+inline uint32_t rotate_bits(uint32_t v, int M, int s)
+{
+    return (v >> s) | ((v & ((1u << s) - 1u)) << (M - s));
+}
+
+// Masks of one layout, in that layout's row coordinates and sorted by x.  With
+// two layouts, a QUAD mask goes to the rotated layout (1) when fewer of its
+// flipped qubits lie outside a tile there; everything else stays in layout 0.
+// A relabelling of qubits keeps every coefficient: only x, zbase and the
+// qubit of each table index bit move.
+std::vector<MaskRec> layout_masks(const std::vector<MaskRec>& masks, int M, int tb, bool two, int layout)
+{
+    std::vector<MaskRec> out;
+    const uint32_t row_mask = (1u << tb) - 1u;
+    for (const MaskRec& m : masks) {
+        int in_b = 0;
+        if (two && (m.type_tab >> 28) == MASK_QUAD) {
+            const int out_a = __builtin_popcount(m.x & ~row_mask);
+            const int out_b = __builtin_popcount(rotate_bits(m.x, M, tb) & ~row_mask);
+            in_b = out_b < out_a;
+        }
+        if (in_b != layout) continue;
+        if (layout == 0) {
+            out.push_back(m);
+            continue;
+        }
+        MaskRec r = m;
+        r.x = rotate_bits(m.x, M, tb);
+        r.zbase = rotate_bits(m.zbase, M, tb);
+        r.qpack = 0;   // table index bit q stays bit q; only its qubit moves
+        for (int q = 0; q < 4; ++q) {
+            const int b = (int)mask_q(m.qpack, q);
+            r.qpack |= (uint32_t)(b >= tb ? b - tb : b + (M - tb)) << (8 * q);
+        }
+        out.push_back(r);
+    }
+    std::stable_sort(out.begin(), out.end(), [](const MaskRec& a, const MaskRec& b) { return a.x < b.x; });
+    return out;
 }
 
 // Mask records for launch shape (tile_bits, nt), in mask order.
@@ -513,19 +607,27 @@ const KRec* krecs_for(const HamiltonianDev& H, const ApplyPlan& P)
 
 namespace {
 
-const HamiltonianDev::ApplyTables& apply_tables_for(const HamiltonianDev& H, const ApplyPlan& P, uint32_t esz)
+const HamiltonianDev::ApplyTables& apply_tables_for(const HamiltonianDev& H, const ApplyPlan& P, uint32_t esz,
+                                                    int layout)
 {
-    const int key = (P.tile_bits * 16 + P.lb) * 32 + (int)esz;
+    const int key = (((P.tile_bits * 16 + P.lb) * 32 + (int)esz) * 2 + P.two_layouts) * 2 + layout;
     auto it = H.apply_tables.find(key);
     if (it == H.apply_tables.end()) {
         std::vector<QApplyChunk> ch;
         std::vector<QRec> rc;
-        build_apply_tables(*H.host_masks, P.tile_bits, P.lb, esz, ch, rc);
+        std::vector<FarRec> far;
+        const std::vector<MaskRec> masks = layout_masks(*H.host_masks, H.M, P.tile_bits, P.two_layouts != 0, layout);
+        build_apply_tables(masks, P.tile_bits, P.lb, esz, ch, rc, far);
         std::unique_ptr<HamiltonianDev::ApplyTables> t(new HamiltonianDev::ApplyTables());
         t->n_chunks = (int)ch.size();
+        t->n_far = (int)far.size();
         if (!ch.empty()) {
             t->chunks.ensure(ch.size() * sizeof(QApplyChunk));
             SYK_HIP(hipMemcpy(t->chunks.p, ch.data(), ch.size() * sizeof(QApplyChunk), hipMemcpyHostToDevice));
+        }
+        if (!far.empty()) {
+            t->far.ensure(far.size() * sizeof(FarRec));
+            SYK_HIP(hipMemcpy(t->far.p, far.data(), far.size() * sizeof(FarRec), hipMemcpyHostToDevice));
         }
         t->recs.ensure(rc.size() * sizeof(QRec));
         SYK_HIP(hipMemcpy(t->recs.p, rc.data(), rc.size() * sizeof(QRec), hipMemcpyHostToDevice));
@@ -555,6 +657,10 @@ ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune)
     if (tune && tune->threads != 0 && tune->threads != (1 << kLaneBits))
         throw Error(SYK_EINVAL, "apply_H: threads must be 0 or 256");
     P.xcd_remap = tune ? tune->xcd_remap : 1;
+    // QUAD masks whose four qubits all lie above the tile would each stream a
+    // whole tile from global memory; with at least C(7,4) of them, run the
+    // masks that sit better in the rotated layout there.
+    P.two_layouts = (M - tb >= 7 && tb >= 8) ? 1 : 0;
     return P;
 }
 
@@ -563,34 +669,54 @@ void launch_apply_h(const HamiltonianDev& H, syk_dtype dtype, int nvec, const in
 {
     const int M = H.M;
     if (P.lb > kLaneBits || (P.rpt > 1 && P.lb != kLaneBits) || P.nt != (1 << P.lb) ||
-        (P.rpt << P.lb) != (1 << P.tile_bits) || P.tile_bits > M)
+        (P.rpt << P.lb) != (1 << P.tile_bits) || P.tile_bits > M ||
+        (P.two_layouts && (P.tile_bits < 5 || M - P.tile_bits < 5)))
         throw Error(SYK_EINVAL, "apply_H: inconsistent launch shape");
-    (void)H.groups_for(P.tile_bits, true);   // builds the far list
-    const FarRec* far = H.far_for(P.tile_bits);
-    const int n_far = H.n_far_for(P.tile_bits);
-    const HamiltonianDev::ApplyTables& A = apply_tables_for(H, P, (uint32_t)elem_bytes(dtype));
+    const size_t esz = elem_bytes(dtype);
+    const uint64_t dim = (uint64_t)1 << M;
+    const HamiltonianDev::ApplyTables& A = apply_tables_for(H, P, (uint32_t)esz, 0);
+    const HamiltonianDev::ApplyTables* B = P.two_layouts ? &apply_tables_for(H, P, (uint32_t)esz, 1) : nullptr;
+    if (B) {
+        const size_t bytes = (size_t)std::min(nvec, kColsPerLaunch) * dim * esz;
+        H.rot_in.ensure(bytes);
+        H.rot_out.ensure(bytes);
+    }
     timing_begin(s);
     for (int sl = 0; sl < P.slices; ++sl) {
         KLayout L{};
-        L.far = far;
-        L.n_far = n_far;
-        L.n_chunks = A.n_chunks;
         L.tile_bits = P.tile_bits;
         L.lane_bits = P.lb;
-        L.dim = (uint64_t)1 << M;
-        L.col0 = sl * kColsPerLaunch;
-        L.n_tiles = (uint32_t)(((uint64_t)1 << M) >> P.tile_bits);
+        L.dim = dim;
+        L.col0 = 0;
+        L.n_tiles = (uint32_t)(dim >> P.tile_bits);
         L.xcd_remap = P.xcd_remap;
-        const int ncols = std::min(kColsPerLaunch, nvec - L.col0);
-        for (int c = 0; c < ncols; ++c) L.real[c] = real_of_col ? real_of_col[L.col0 + c] : 0;
-        const auto* ch = A.chunks.as<QApplyChunk>();
-        const auto* rc = A.recs.as<QRec>();
-        if (dtype == SYK_C128) {
-            KTerms<double> T{H.tab4_d, H.qinfo, H.phi2_d, H.w2_d, H.dz, H.dw_d, H.n_diag, H.n_real, M};
-            launch_t<double>(P, T, ch, rc, L, ncols, psi, out, s);
+        const int col0 = sl * kColsPerLaunch;
+        const int ncols = std::min(kColsPerLaunch, nvec - col0);
+        for (int c = 0; c < ncols; ++c) L.real[c] = real_of_col ? real_of_col[col0 + c] : 0;
+        const char* in_c = static_cast<const char*>(psi) + (size_t)col0 * dim * esz;
+        char* out_c = static_cast<char*>(out) + (size_t)col0 * dim * esz;
+        auto run = [&](const HamiltonianDev::ApplyTables& Tb, const void* src, void* dst) {
+            L.far = Tb.far.as<FarRec>();
+            L.n_far = Tb.n_far;
+            L.n_chunks = Tb.n_chunks;
+            const auto* ch = Tb.chunks.as<QApplyChunk>();
+            const auto* rc = Tb.recs.as<QRec>();
+            if (dtype == SYK_C128) {
+                KTerms<double> T{H.tab4_d, H.qinfo, H.phi2_d, H.w2_d, H.dz, H.dw_d, H.n_diag, H.n_real, M};
+                launch_t<double>(P, T, ch, rc, L, ncols, src, dst, s);
+            } else {
+                KTerms<float> T{H.tab4_f, H.qinfo, H.phi2_f, H.w2_f, H.dz, H.dw_f, H.n_diag, H.n_real, M};
+                launch_t<float>(P, T, ch, rc, L, ncols, src, dst, s);
+            }
+        };
+        if (B) {
+            // rows r -> rotate_bits(r): a [2^(M-s)] x [2^s] transpose
+            launch_transpose(dtype, in_c, H.rot_in.p, M - P.tile_bits, P.tile_bits, ncols, dim, false, s);
+            run(*B, H.rot_in.p, H.rot_out.p);
+            run(A, in_c, out_c);
+            launch_transpose(dtype, H.rot_out.p, out_c, P.tile_bits, M - P.tile_bits, ncols, dim, true, s);
         } else {
-            KTerms<float> T{H.tab4_f, H.qinfo, H.phi2_f, H.w2_f, H.dz, H.dw_f, H.n_diag, H.n_real, M};
-            launch_t<float>(P, T, ch, rc, L, ncols, psi, out, s);
+            run(A, in_c, out_c);
         }
     }
     timing_end(s);

@@ -73,6 +73,7 @@ struct ApplyPlan {
     int lb;          // lane bits: nt = 2^lb
     int rpt;         // tile rows per thread
     int xcd_remap;
+    int two_layouts; // also run the masks that flip few rows of a tile on a bit-rotated copy
 };
 
 ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune);

@@ -40,10 +40,12 @@ struct HamiltonianDev {
     mutable std::map<int, std::unique_ptr<DevBuf>> krecs;
     // Per-launch-shape chunks and class-sorted records of the apply kernel.
     struct ApplyTables {
-        DevBuf chunks, recs;
-        int n_chunks = 0;
+        DevBuf chunks, recs, far;
+        int n_chunks = 0, n_far = 0;
     };
     mutable std::map<int, std::unique_ptr<ApplyTables>> apply_tables;
+    // Rotated copies of psi and of the second layout's output (two-layout plans).
+    mutable DevBuf rot_in, rot_out;
 };
 
 // Named device workspaces, grown on demand and kept until the handle dies.
