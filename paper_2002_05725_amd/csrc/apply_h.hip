@@ -154,7 +154,6 @@ __global__ void __launch_bounds__(256) k_apply(KTerms<R> T, const QApplyChunk* _
     const uint32_t lb = (RPT > 1) ? (uint32_t)kLaneBits : (uint32_t)L.lane_bits;
     const uint32_t nt = 1u << lb;
     const uint32_t tile = tile_of_block(blockIdx.x, L);
-    const uint32_t kmask = (uint32_t)(RPT - 1) << lb;   // row bits that vary with k
     const uint32_t tid = threadIdx.x;
     const int rc = L.real[blockIdx.y];
     const int M = T.M;
@@ -201,6 +200,19 @@ __global__ void __launch_bounds__(256) k_apply(KTerms<R> T, const QApplyChunk* _
             o.im = flip(c.im, sg);
             S.tabs[e] = o;
         }
+        // PAIR slots (after the QUAD tables): for each row k and term e, the part
+        // of L_e(r) that does not depend on the lane, W_e + sum over tile and k
+        // bits c of w_{e,c} r_c.  One slot holds RPT * 4 values.
+        for (uint32_t v = tid; v < C.n_pair * (RPT * 4); v += nt) {
+            const uint32_t p = v / (RPT * 4), k = (v >> 2) % RPT, e = v & 3u;
+            const uint32_t tab = rec[C.first + C.n_quad + p].tab;
+            const R* w = T.w2 + (((size_t)tab * T.n_real + rc) * 4 + e) * (M + 1);
+            const uint32_t rb = base | (k << lb);
+            R acc = w[M];
+            for (int c = (int)lb; c < M; ++c)
+                if ((rb >> c) & 1u) acc += w[c];
+            reinterpret_cast<R*>(S.tabs)[(C.n_quad + p) * (16 * esz / sizeof(R)) + k * 4 + e] = acc;
+        }
         __syncthreads();
 
         uint32_t mi = C.first;
@@ -240,44 +252,36 @@ __global__ void __launch_bounds__(256) k_apply(KTerms<R> T, const QApplyChunk* _
         for_each_class(quad_class, std::make_integer_sequence<int, ipow3(KB)>{});
 
         // PAIR: D = (-1)^{|r & zbase|} sum_e phi_e (-1)^{s_q0 e_0 + s_q1 e_1} L_e(r),
-        // phi_e = Phi[idx = 3][e] (the entry with s_q0 = s_q1 = 0),
-        // L_e(r) = W_e + sum_c w_{e,c} r_c split into lane/tile bits (once)
-        // and k bits (per k).
+        // phi_e = Phi[idx = 3][e] (the entry with s_q0 = s_q1 = 0), L_e(r) =
+        // W_e + sum_c w_{e,c} r_c: the lane bits here, the rest staged per row k.
         for (uint32_t i = 0; i < C.n_pair; ++i, ++mi) {
             const QRec q = rec[mi];
             const R* w = T.w2 + ((size_t)q.tab * T.n_real + rc) * 4 * (M + 1);
             const cplx<R>* ph = T.phi2 + (size_t)q.tab * 16 + 12;
-            R l0 = w[M], l1 = w[(M + 1) + M], l2 = w[2 * (M + 1) + M], l3 = w[3 * (M + 1) + M];
-            for (int c = 0; c < M; ++c) {
-                if ((1u << c) & kmask) continue;
-                const R b = (R)bit(tid | base, c);
-                l0 = fma(w[c], b, l0);
-                l1 = fma(w[(M + 1) + c], b, l1);
-                l2 = fma(w[2 * (M + 1) + c], b, l2);
-                l3 = fma(w[3 * (M + 1) + c], b, l3);
+            R l[4] = {R(0), R(0), R(0), R(0)};
+#pragma unroll
+            for (int c = 0; c < kLaneBits; ++c) {
+                if (c >= (int)lb) break;
+                const R b = (R)((tid >> c) & 1u);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) l[e] = fma(w[e * (M + 1) + c], b, l[e]);
             }
-            const uint32_t sl = parity(tid & q.zbase);
             const uint32_t q0 = mask_q(q.qpack, 0), q1 = mask_q(q.qpack, 1);
+            const uint32_t rl = tid | base;
+            const uint32_t sa_l = bit(rl, q0) ^ 1u, sb_l = bit(rl, q1) ^ 1u, s_l = parity(rl & q.zbase);
             const uint32_t sb = tid_b ^ q.xoff;
+            const R* tk = reinterpret_cast<const R*>(tab_b + (C.n_quad + i) * 16u * esz);
 #pragma unroll
             for (int k = 0; k < RPT; ++k) {
-                const uint32_t ru = base | ((uint32_t)k << lb);
-                R k0 = l0, k1 = l1, k2 = l2, k3 = l3;
-                for (uint32_t rb = ru & kmask; rb; rb &= rb - 1) {
-                    const int c = __ffs(rb) - 1;
-                    k0 += w[c];
-                    k1 += w[(M + 1) + c];
-                    k2 += w[2 * (M + 1) + c];
-                    k3 += w[3 * (M + 1) + c];
-                }
-                const uint32_t r = tid | ru;
-                const uint32_t sa = bit(r, q0) ^ 1u, sbb = bit(r, q1) ^ 1u;
-                k1 = flip(k1, sa);
-                k2 = flip(k2, sbb);
-                k3 = flip(k3, sa ^ sbb);
-                const uint32_t s = sl ^ parity(ru & q.zbase);
-                const R dre = flip(ph[0].re * k0 + ph[1].re * k1 + ph[2].re * k2 + ph[3].re * k3, s);
-                const R dim = flip(ph[0].im * k0 + ph[1].im * k1 + ph[2].im * k2 + ph[3].im * k3, s);
+                const uint32_t kr = (uint32_t)k << lb;
+                const uint32_t sa = sa_l ^ bit(kr, q0), sbb = sb_l ^ bit(kr, q1);
+                const uint32_t s = s_l ^ parity(kr & q.zbase);
+                const R a0 = l[0] + tk[k * 4 + 0];
+                const R a1 = flip(l[1] + tk[k * 4 + 1], sa);
+                const R a2 = flip(l[2] + tk[k * 4 + 2], sbb);
+                const R a3 = flip(l[3] + tk[k * 4 + 3], sa ^ sbb);
+                const R dre = flip(ph[0].re * a0 + ph[1].re * a1 + ph[2].re * a2 + ph[3].re * a3, s);
+                const R dim = flip(ph[0].im * a0 + ph[1].im * a1 + ph[2].im * a2 + ph[3].im * a3, s);
                 const cplx<R> v = src_at(sb + (((uint32_t)k ^ q.koffs) << lb) * esz);
                 cmac(pr[k], pi[k], dre, dim, v);
             }
