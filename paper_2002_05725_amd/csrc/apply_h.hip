@@ -114,10 +114,14 @@ __device__ __forceinline__ void for_each_class(F& f, std::integer_sequence<int, 
     (f(std::integral_constant<int, I>{}), ...);
 }
 
+// Masks per chunk of the apply kernel: complex128 keeps the LDS of a
+// 2048-row tile at 40 KiB so that four workgroups share a CU.
+constexpr int apply_chunk_masks(uint32_t esz) { return esz == 16 ? 32 : 64; }
+
 template <typename R, int RPT>
 struct ApplyLds {
     cplx<R> src[RPT << kLaneBits];
-    cplx<R> tabs[kChunkMasks * 16];
+    cplx<R> tabs[apply_chunk_masks(sizeof(cplx<R>)) * 16];
 };
 
 // Sign flip by a word whose bit 31 is the sign to apply (other bits zero).
@@ -137,7 +141,8 @@ __device__ __forceinline__ void cmac(R& pr, R& pi, R a, R b, const cplx<R>& v)
 }
 
 template <typename R, int RPT>
-__global__ void __launch_bounds__(256) k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 && RPT == 8 ? 4 : 1)))
+k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
                                                const QRec* __restrict__ rec, KLayout L,
                                                const cplx<R>* __restrict__ psi, cplx<R>* __restrict__ out)
 {
@@ -459,10 +464,10 @@ void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int la
     size_t i = 0;
     uint32_t prev_high = 0xffffffffu;
     while (i < masks.size()) {
-        // masks of one chunk: same x_high, at most kChunkMasks
+        // masks of one chunk: same x_high, at most apply_chunk_masks(esz)
         std::vector<uint32_t> mem;
         const uint32_t xh = masks[i].x >> tile_bits;
-        while (i < masks.size() && (masks[i].x >> tile_bits) == xh && mem.size() < (size_t)kChunkMasks) {
+        while (i < masks.size() && (masks[i].x >> tile_bits) == xh && mem.size() < (size_t)apply_chunk_masks(esz)) {
             const MaskRec& m = masks[i];
             if (type_of(m) == MASK_QUAD && (m.x & row_mask) == 0u)
                 far.push_back({m.x >> tile_bits, m.qpack, m.zbase, m.type_tab & 0x0fffffffu});
