@@ -8,10 +8,14 @@ combination) of one complex128 state by dt = 0.25.
 
 Printed: one JSON line with the OTOC time-steps/s (value); the apply_H figures
 (algorithmic bytes of one apply over its HIP-event-timed duration, against
-8 TB/s, in "apply_H"; the same duration against the ALU issue roof in
+8 TB/s, in "apply_H"; the same duration against the FP64 vector-ALU roof in
 "roofline", with the rocprofv3-measured HBM bytes when they were taken on the
 current kernel source); the complex64 leg; and the CPU checker timed on a
 bounded sample of rows of the same apply.
+
+One apply_H call is the unit of work of the roofline: the apply kernel over
+the masks of the natural row layout, the same kernel over the masks of the
+bit-rotated layout, and the two transposes between the layouts.
 """
 from __future__ import annotations
 
@@ -27,13 +31,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# ALU roof of apply_H: 256 CUs x 64 lanes x 2.4 GHz lane-operations per second
-# (an FP64 FMA issues at the INT32 rate on gfx950: 78.6 TFLOP/s = 39.3 T FMA/s).
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Elementary operations per (row, flip mask) of the grouped product: source
-# index r ^ x (1), the four table-index bits (4), the sign parity of r & zbase
-# (2), and the complex multiply-accumulate (4 FMA).
-OPS_PER_PAIR = 11
+# Vector-ALU roofs of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x
+# 2.4 GHz = 78.6 TFLOP/s in FP64; FP32 doubles that only with packed FP32
+# instructions, which this build does not emit.
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# Arithmetic per (row, flip mask) pair of the grouped product: one complex
+# multiply-accumulate, coefficient x gathered amplitude = 4 real FMA = 8 flops.
+FLOPS_PER_PAIR = 8
 METRIC = "apply_H GB/s (% HBM peak) and OTOC time-steps/s at N=52; grad/fwd cost ratio"
 
 
@@ -214,7 +219,7 @@ def main():
     avg_apply_s = apply_ms / n_apply / 1e3
     alg_bytes = (T.n_masks + 1) * D * 16
     achieved = alg_bytes / avg_apply_s / 1e9
-    alu_tops = OPS_PER_PAIR * T.n_masks * D / avg_apply_s / 1e12
+    alu_tflops = FLOPS_PER_PAIR * T.n_masks * D / avg_apply_s / 1e12
     log(f"[bench] c128: {ms_step:.0f} ms/step, apply {avg_apply_s * 1e3:.1f} ms ({achieved:.0f} GB/s alg)")
 
     c64 = None
@@ -232,6 +237,8 @@ def main():
             "apply_alg_GBps": (T.n_masks + 1) * D * 8 / a64 / 1e9,
         }
         c64["apply_pct_hbm_peak"] = 100 * c64["apply_alg_GBps"] / HBM_PEAK_GBS
+        c64["apply_TFLOPs"] = FLOPS_PER_PAIR * T.n_masks * D / a64 / 1e12
+        c64["apply_frac_fp32_vector_peak"] = c64["apply_TFLOPs"] / FP32_VECTOR_PEAK_TFLOPS
         del p64
         log(f"[bench] c64: {c64['ms_per_step']:.0f} ms/step, apply {a64 * 1e3:.1f} ms")
 
@@ -277,13 +284,16 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "achieved": alu_tops,
-            "peak": ALU_PEAK_TOPS,
-            "unit": "TOP/s",
-            "frac": alu_tops / ALU_PEAK_TOPS,
+            "achieved": alu_tflops,
+            "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": alu_tflops / FP64_VECTOR_PEAK_TFLOPS,
             "traffic": traffic,
-            "ops_model": f"{OPS_PER_PAIR} lane-operations per (row, flip mask) pair, n_masks * dim pairs",
-            "traffic_unit": "bytes per apply (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "flops_model": f"{FLOPS_PER_PAIR} flops (one complex FMA) per (row, flip mask) pair, n_masks * dim "
+                           "pairs per apply_H call",
+            "unit_of_work": "one apply_H call (k_apply natural layout + k_apply rotated layout + 2 transposes), "
+                            "HIP events on the call's stream",
+            "traffic_unit": "bytes per apply_H call (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },
         "complex64": c64,
         "batched": batched,
