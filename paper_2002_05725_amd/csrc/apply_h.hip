@@ -17,6 +17,7 @@
 #include <utility>
 
 #include "apply_h.hpp"
+#include "mask_classes.hpp"
 #include "timing.hpp"
 
 namespace syk {
@@ -95,25 +96,6 @@ namespace {
 // (v_dot4), the lane part of the sign one popcount.
 constexpr int kLaneBits = 8;
 
-constexpr int class_bits(int cls, int kb, int digit)
-{
-    int r = 0;
-    for (int b = 0; b < kb; ++b) {
-        if (cls % 3 == digit) r |= 1 << b;
-        cls /= 3;
-    }
-    return r;
-}
-
-constexpr int ipow3(int n) { return n == 0 ? 1 : 3 * ipow3(n - 1); }
-constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
-
-template <typename F, int... I>
-__device__ __forceinline__ void for_each_class(F& f, std::integer_sequence<int, I...>)
-{
-    (f(std::integral_constant<int, I>{}), ...);
-}
-
 // Masks per chunk of the apply kernel: complex128 keeps the LDS of a
 // 2048-row tile at 40 KiB so that four workgroups share a CU.
 constexpr int apply_chunk_masks(uint32_t esz) { return esz == 16 ? 32 : 64; }
@@ -123,13 +105,6 @@ struct ApplyLds {
     cplx<R> src[RPT << kLaneBits];
     cplx<R> tabs[apply_chunk_masks(sizeof(cplx<R>)) * 16];
 };
-
-// Sign flip by a word whose bit 31 is the sign to apply (other bits zero).
-__device__ __forceinline__ double flip31(double x, uint32_t s)
-{
-    return __hiloint2double(__double2hiint(x) ^ (int)s, __double2loint(x));
-}
-__device__ __forceinline__ float flip31(float x, uint32_t s) { return __int_as_float(__float_as_int(x) ^ (int)s); }
 
 template <typename R>
 __device__ __forceinline__ void cmac(R& pr, R& pi, R a, R b, const cplx<R>& v)
@@ -221,7 +196,7 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
         __syncthreads();
 
         uint32_t mi = C.first;
-        auto quad_class = [&](auto cls) {
+        auto class_loop = [&](auto cls) {
             constexpr int CL = decltype(cls)::value;
             constexpr uint32_t XK = (uint32_t)class_bits(CL, KB, 1);   // k bits the masks flip
             constexpr uint32_t ZK = (uint32_t)class_bits(CL, KB, 2);   // k bits in their Z string
@@ -254,7 +229,7 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
                 }
             }
         };
-        for_each_class(quad_class, std::make_integer_sequence<int, ipow3(KB)>{});
+        for_each_class(class_loop, std::make_integer_sequence<int, ipow3(KB)>{});
 
         // PAIR: D = (-1)^{|r & zbase|} sum_e phi_e (-1)^{s_q0 e_0 + s_q1 e_1} L_e(r),
         // phi_e = Phi[idx = 3][e] (the entry with s_q0 = s_q1 = 0), L_e(r) =
@@ -451,15 +426,7 @@ void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int la
     const int kb = tile_bits - lane_bits;
     if (kb < 0 || kb > kMaxKBits) throw Error(SYK_EINVAL, "apply_H: unsupported rows per thread");
     const uint32_t kbits_mask = (1u << kb) - 1u;
-    auto quad_class = [&](const MaskRec& m) {
-        int cls = 0, p3 = 1;
-        for (int b = 0; b < kb; ++b, p3 *= 3) {
-            const uint32_t q = (uint32_t)(lane_bits + b);
-            if ((m.x >> q) & 1u) cls += p3;
-            else if ((m.zbase >> q) & 1u) cls += 2 * p3;
-        }
-        return cls;
-    };
+    auto quad_class_of = [&](const MaskRec& m) { return quad_class(m.x, m.zbase, lane_bits, kb); };
     auto type_of = [](const MaskRec& m) { return m.type_tab >> 28; };
     size_t i = 0;
     uint32_t prev_high = 0xffffffffu;
@@ -479,7 +446,7 @@ void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int la
         auto key = [&](uint32_t j) {
             const MaskRec& m = masks[j];
             const uint32_t t = type_of(m);
-            return t == MASK_QUAD ? quad_class(m) : t == MASK_PAIR ? 100 : 200;
+            return t == MASK_QUAD ? quad_class_of(m) : t == MASK_PAIR ? 100 : 200;
         };
         std::stable_sort(mem.begin(), mem.end(), [&](uint32_t a, uint32_t b) { return key(a) < key(b); });
         QApplyChunk c{};
@@ -498,7 +465,7 @@ void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int la
             r.qpack = m.qpack;
             r.zbase = m.zbase;
             if (t == MASK_QUAD) {
-                const int cls = quad_class(m);
+                const int cls = quad_class_of(m);
                 ++c.n_quad;
                 c.cnt[cls >> 2] += 1u << (8 * (cls & 3));
                 for (int q = 0; q < 4; ++q) {
@@ -592,6 +559,7 @@ std::vector<KRec> build_krecs(const std::vector<MaskRec>& masks, const std::vect
         if (tab >= (1u << 26)) throw Error(SYK_EUNSUPPORTED, "apply_H: too many masks");
         k.meta = type << 28 | path << 26 | tab;
         k.pad[0] = (uint32_t)bin_off[i];
+        k.pad[1] = m.x >> tile_bits;
         out[i] = k;
     }
     return out;

@@ -14,7 +14,7 @@ struct alignas(16) KRec {
     uint32_t zbase;     // Z string of the mask
     uint32_t meta;      // type << 28 | path << 26 | table index
     uint32_t kinfo[2];  // QUAD, per row k: (index bits from k | sign bit from k << 4) << 5 (k % 6)
-    uint32_t pad[2];    // pad[0]: first derivative bin of the mask
+    uint32_t pad[2];    // pad[0]: first derivative bin of the mask; pad[1]: x >> tile_bits
 };
 static_assert(sizeof(KRec) == 32, "KRec layout");
 

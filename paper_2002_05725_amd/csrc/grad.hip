@@ -9,9 +9,18 @@
 // workgroup sweeps a fixed set of tiles for one chunk of masks at a time with
 // the chunk's bins in LDS, then writes them to its own slice of a partial
 // buffer; k_bins_reduce adds the slices in a fixed order.
+//
+// QUAD bins depend on the row only through its bits at the four flipped
+// qubits: the lanes of a wave that agree on those bits are summed with a
+// butterfly of lane exchanges first, and one lane per bin adds to LDS.  PAIR
+// and DIAG bins are linear in sum_p w_p conj(g_p[r]) v_p[r ^ x], which each
+// thread sums over the pairs in registers and bins once per tile.
 #include "grad.hpp"
 
+#include <algorithm>
 #include <cstring>
+
+#include "mask_classes.hpp"
 
 namespace syk {
 
@@ -27,6 +36,34 @@ __device__ __forceinline__ uint32_t quad_index(uint32_t r, uint32_t qpack)
 {
     return bit(r, mask_q(qpack, 0)) | (bit(r, mask_q(qpack, 1)) << 1) | (bit(r, mask_q(qpack, 2)) << 2) |
            (bit(r, mask_q(qpack, 3)) << 3);
+}
+
+// v from the lane whose index differs from this lane's in bit B (B < 6).
+template <int B>
+__device__ __forceinline__ double lane_xor(double v)
+{
+    if constexpr (B < 5) {
+        // ds_swizzle bit mode: and_mask 0x1f, or_mask 0, xor_mask 1 << B
+        constexpr int pat = 0x1f | ((1 << B) << 10);
+        const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), pat);
+        const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), pat);
+        return __hiloint2double(hi, lo);
+    } else {
+        return __shfl_xor(v, 32);
+    }
+}
+
+// Sum of v over the lanes of this wave that agree with this lane on every
+// in-wave lane bit set in keep (bits 0..5 of the lane index).
+__device__ __forceinline__ double group_sum(double v, uint32_t keep)
+{
+    if (!(keep & 1u)) v += lane_xor<0>(v);
+    if (!(keep & 2u)) v += lane_xor<1>(v);
+    if (!(keep & 4u)) v += lane_xor<2>(v);
+    if (!(keep & 8u)) v += lane_xor<3>(v);
+    if (!(keep & 16u)) v += lane_xor<4>(v);
+    if (!(keep & 32u)) v += lane_xor<5>(v);
+    return v;
 }
 
 // out = b (w - gamma y) + s z + c x ; acc += ca out (acc optional).  Null
@@ -73,6 +110,7 @@ __global__ void __launch_bounds__(256) k_cheb_rec(cplx<R>* out, const cplx<R>* _
 struct GLayout {
     int tile_bits;
     uint32_t n_tiles;
+    uint32_t tile_groups, chunk_groups;   // grid = tile_groups x chunk_groups workgroups
     int n_chunks;
     int npairs;
     int M;
@@ -82,115 +120,207 @@ struct GLayout {
 
 template <int RPT>
 __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec, const GChunk* __restrict__ chunks,
+                                                    const uint32_t* __restrict__ members,
+                                                    const uint32_t* __restrict__ local,
+                                                    const GRec* __restrict__ grec,
                                                     const uint32_t* __restrict__ dz, GLayout L,
                                                     const c128* const* __restrict__ gs,
                                                     const c128* const* __restrict__ vs,
                                                     const double* __restrict__ wts, double* __restrict__ partial)
 {
+    constexpr int KB = ilog2c(RPT);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const uint32_t nt = blockDim.x;
+    const uint32_t lb = 31u - __clz(nt);                              // lane bits (8 when RPT > 1)
     const uint32_t tile_elems = nt * RPT;
     c128* src = reinterpret_cast<c128*>(smem_raw);
     double* bins = reinterpret_cast<double*>(src + tile_elems);     // [kGradBinCap][2]
+    uint32_t* fold = reinterpret_cast<uint32_t*>(bins + 2 * kGradBinCap);   // [kChunkMasks]
     const uint32_t tid = threadIdx.x;
-    const uint32_t row_mask = (1u << L.tile_bits) - 1u;
-    const uint32_t kmask = row_mask & ~(nt - 1u);
-    double* mine = partial + (uint64_t)blockIdx.x * L.n_bins * 2;
+    // bits 0..3 and 4..7 of tid, one per byte (table-index gather)
+    uint32_t B0 = 0, B1 = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        B0 |= ((tid >> i) & 1u) << (8 * i);
+        B1 |= ((tid >> (4 + i)) & 1u) << (8 * i);
+    }
+    // workgroup (t, s) of the grid: tiles t, t + tile_groups, ...; chunks s, s + chunk_groups, ...
+    const uint32_t tg = blockIdx.x % L.tile_groups, sg = blockIdx.x / L.tile_groups;
+    double* mine = partial + (uint64_t)tg * L.n_bins * 2;
 
-    for (int ch = 0; ch < L.n_chunks; ++ch) {
+    for (int ch = (int)sg; ch < L.n_chunks; ch += (int)L.chunk_groups) {
         const GChunk C = chunks[ch];
         for (uint32_t e = tid; e < 2 * C.bin_count; e += nt) bins[e] = 0.0;
-        for (uint32_t tile = blockIdx.x; tile < L.n_tiles; tile += gridDim.x) {
+        for (uint32_t tile = tg; tile < L.n_tiles; tile += L.tile_groups) {
             const uint32_t base = tile << L.tile_bits;
+            if (!C.far) {
+                // tile part of each QUAD member's bin index and sign
+                __syncthreads();   // the previous tile's readers of fold are done
+                for (uint32_t j = tid; j < C.n_quad; j += nt) {
+                    const KRec m = krec[members[C.first + j]];
+                    fold[j] = quad_index(base, m.qpack) | (parity(base & m.zbase) << 4);
+                }
+            }
+            // PAIR / DIAG: sum_p w_p conj(g_p[r]) v_p[r ^ x] for the thread's rows
+            double acc_re[kGradAccMasks][RPT], acc_im[kGradAccMasks][RPT];
+#pragma unroll
+            for (int j = 0; j < kGradAccMasks; ++j)
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) acc_re[j][k] = acc_im[j][k] = 0.0;
+
             for (int p = 0; p < L.npairs; ++p) {
                 const c128* __restrict__ g = gs[p];
                 const c128* __restrict__ v = vs[p];
                 const double wt = wts[p];
-                c128 gk[RPT];
+                c128 gk[RPT];   // w_p g_p on the thread's rows
 #pragma unroll
-                for (int k = 0; k < RPT; ++k) gk[k] = g[base + tid + k * nt];
-                __syncthreads();   // previous users of src are done
-                const uint64_t sbase = (uint64_t)(tile ^ C.x_high) << L.tile_bits;
+                for (int k = 0; k < RPT; ++k) {
+                    gk[k] = g[base + tid + k * nt];
+                    gk[k].re *= wt;
+                    gk[k].im *= wt;
+                }
+                if (!C.far) {
+                    __syncthreads();   // previous users of src are done
+                    const uint64_t sbase = (uint64_t)(tile ^ C.x_high) << L.tile_bits;
 #pragma unroll
-                for (int k = 0; k < RPT; ++k) src[tid + k * nt] = v[sbase + tid + k * nt];
-                __syncthreads();
+                    for (int k = 0; k < RPT; ++k) src[tid + k * nt] = v[sbase + tid + k * nt];
+                    __syncthreads();
+                }
+                // source row k of a mask: staged tile, or (far chunks) the mask's own tile
+                auto source = [&](const KRec& m, int k) -> c128 {
+                    if (C.far) return v[((uint64_t)(tile ^ m.pad[1]) << L.tile_bits) + tid + k * nt];
+                    return src[(tid + k * nt) ^ m.xl];
+                };
 
-                for (uint32_t mi = C.first; mi < C.first + C.count; ++mi) {
-                    const KRec m = krec[mi];
-                    const uint32_t type = m.meta >> 28;
-                    double* mb = bins + 2 * (m.pad[0] - C.bin_begin);
-                    if (type == MASK_QUAD) {
-                        const uint32_t path = (m.meta >> 26) & 3u;
-                        const uint32_t il = quad_index(tid, m.qpack) | quad_index(base, m.qpack);
-                        const uint32_t sl = parity(tid & m.zbase) ^ parity(base & m.zbase);
-                        if (path != PATH_FULL) {
-                            double ar = 0.0, ai = 0.0;
-#pragma unroll
-                            for (int k = 0; k < RPT; ++k) {
-                                const uint32_t sk = (m.kinfo[k / 6] >> (5 * (k % 6) + 4)) & 1u;
-                                const c128 x = src[(tid + k * nt) ^ m.xl];
-                                // conj(g) x with the row's sign
-                                const double pr = gk[k].re * x.re + gk[k].im * x.im;
-                                const double pi = gk[k].re * x.im - gk[k].im * x.re;
-                                ar += flip(pr, sk);
-                                ai += flip(pi, sk);
-                            }
-                            const uint32_t idx = il | (m.kinfo[0] & 15u);
-                            atomicAdd(&mb[2 * idx], wt * flip(ar, sl));
-                            atomicAdd(&mb[2 * idx + 1], wt * flip(ai, sl));
-                        } else {
-#pragma unroll
-                            for (int k = 0; k < RPT; ++k) {
-                                const uint32_t ki = (m.kinfo[k / 6] >> (5 * (k % 6))) & 31u;
-                                const c128 x = src[(tid + k * nt) ^ m.xl];
-                                const uint32_t s = sl ^ (ki >> 4);
-                                const double pr = gk[k].re * x.re + gk[k].im * x.im;
-                                const double pi = gk[k].re * x.im - gk[k].im * x.re;
-                                const uint32_t idx = il | (ki & 15u);
-                                atomicAdd(&mb[2 * idx], wt * flip(pr, s));
-                                atomicAdd(&mb[2 * idx + 1], wt * flip(pi, s));
-                            }
-                        }
-                    } else if (type == MASK_PAIR) {
-                        const uint32_t q0 = mask_q(m.qpack, 0), q1 = mask_q(m.qpack, 1);
+                if (C.far) {
+                    // far QUAD masks: every row of the tile has the same bin and sign
+                    for (uint32_t j = C.first; j < C.first + C.count; ++j) {
+                        const KRec m = krec[members[j]];
+                        if ((m.meta >> 28) != MASK_QUAD) continue;
+                        double ar = 0.0, ai = 0.0;
 #pragma unroll
                         for (int k = 0; k < RPT; ++k) {
-                            const uint32_t r = base | tid | (k * nt);
-                            const c128 x = src[(tid + k * nt) ^ m.xl];
-                            const uint32_t s = parity(r & m.zbase);
-                            const double pr = wt * flip(gk[k].re * x.re + gk[k].im * x.im, s);
-                            const double pi = wt * flip(gk[k].re * x.im - gk[k].im * x.re, s);
-                            const uint32_t idx = bit(r, q0) | (bit(r, q1) << 1);
-                            atomicAdd(&mb[2 * idx], pr);
-                            atomicAdd(&mb[2 * idx + 1], pi);
-                            for (uint32_t rb = r & ((1u << L.M) - 1u); rb; rb &= rb - 1) {
-                                const uint32_t c = __ffs(rb) - 1;
-                                atomicAdd(&mb[2 * (4 + 4 * c + idx)], pr);
-                                atomicAdd(&mb[2 * (4 + 4 * c + idx) + 1], pi);
+                            const c128 x = source(m, k);
+                            ar += gk[k].re * x.re + gk[k].im * x.im;
+                            ai += gk[k].re * x.im - gk[k].im * x.re;
+                        }
+                        const uint32_t s = parity(base & m.zbase);
+                        ar = group_sum(flip(ar, s), 0u);
+                        ai = group_sum(flip(ai, s), 0u);
+                        if ((tid & 63u) == 0u) {
+                            double* mb = bins + 2 * local[j];
+                            const uint32_t idx = quad_index(base, m.qpack);
+                            atomicAdd(&mb[2 * idx], ar);
+                            atomicAdd(&mb[2 * idx + 1], ai);
+                        }
+                    }
+                } else {
+                    // near QUAD members, class by class
+                    uint32_t j = C.first;
+                    auto class_loop = [&](auto cls) {
+                        constexpr int CL = decltype(cls)::value;
+                        constexpr uint32_t XK = (uint32_t)class_bits(CL, KB, 1);   // k bits the masks flip
+                        constexpr uint32_t ZK = (uint32_t)class_bits(CL, KB, 2);   // k bits in their Z string
+                        const uint32_t n = (C.cnt[CL >> 2] >> (8 * (CL & 3))) & 0xffu;
+                        for (uint32_t i = 0; i < n; ++i, ++j) {
+                            const GRec q = grec[j];
+                            const uint32_t slot = j - C.first;
+                            const uint32_t fo = fold[slot];
+                            const uint32_t il = __builtin_amdgcn_udot4(__builtin_amdgcn_perm(B1, B0, q.sel), 0x08040201u,
+                                                                       fo & 15u, false);
+                            const uint32_t sl = ((uint32_t)__popc(tid & q.zl) ^ (fo >> 4)) << 31;
+                            const uint32_t keep = q.koffs >> 24;
+                            double er[RPT], ei[RPT];   // by the flipped k bits p = k & XK
+#pragma unroll
+                            for (int pp = 0; pp < RPT; ++pp) er[pp] = ei[pp] = 0.0;
+                            const uint32_t sb = tid ^ q.xoff;
+#pragma unroll
+                            for (int k = 0; k < RPT; ++k) {
+                                const c128 x = src[sb + (((uint32_t)k ^ XK) << lb)];
+                                const bool neg = (__builtin_popcount((uint32_t)k & ZK) & 1) != 0;
+                                const double pr = gk[k].re * x.re + gk[k].im * x.im;
+                                const double pi = gk[k].re * x.im - gk[k].im * x.re;
+                                er[k & (int)XK] += neg ? -pr : pr;
+                                ei[k & (int)XK] += neg ? -pi : pi;
+                            }
+                            const bool rep = ((tid & 63u) & ~keep) == 0u;   // one lane per bin and wave
+#pragma unroll
+                            for (int pp = 0; pp < RPT; ++pp) {
+                                if ((pp & ~(int)XK) != 0) continue;
+                                const double ar = group_sum(flip31(er[pp], sl), keep);
+                                const double ai = group_sum(flip31(ei[pp], sl), keep);
+                                uint32_t idx = il;
+#pragma unroll
+                                for (int b = 0; b < KB; ++b)
+                                    if ((pp >> b) & 1) idx += (q.koffs >> (8 * b)) & 0xffu;
+                                if (rep) {
+                                    atomicAdd(&bins[2 * (16 * slot + idx)], ar);
+                                    atomicAdd(&bins[2 * (16 * slot + idx) + 1], ai);
+                                }
                             }
                         }
-                    } else {  // MASK_DIAG
+                    };
+                    for_each_class(class_loop, std::make_integer_sequence<int, ipow3(KB)>{});
+                }
 #pragma unroll
-                        for (int k = 0; k < RPT; ++k) {
-                            const uint32_t r = base | tid | (k * nt);
-                            const c128 x = src[tid + k * nt];
-                            const double pr = wt * (gk[k].re * x.re + gk[k].im * x.im);
-                            const double pi = wt * (gk[k].re * x.im - gk[k].im * x.re);
-                            for (int n = 0; n < L.n_diag; ++n) {
-                                const uint32_t s = parity(r & dz[n]);
-                                atomicAdd(&mb[2 * n], flip(pr, s));
-                                atomicAdd(&mb[2 * n + 1], flip(pi, s));
-                            }
+                for (int j = 0; j < kGradAccMasks; ++j) {
+                    if (j >= (int)C.n_acc) break;
+                    const KRec ma = krec[members[C.first + C.acc[j]]];
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) {
+                        const c128 x = source(ma, k);
+                        acc_re[j][k] += gk[k].re * x.re + gk[k].im * x.im;
+                        acc_im[j][k] += gk[k].re * x.im - gk[k].im * x.re;
+                    }
+                }
+            }
+
+            // bins of the PAIR / DIAG masks from the pair sums of this tile
+#pragma unroll
+            for (int j = 0; j < kGradAccMasks; ++j) {
+                if (j >= (int)C.n_acc) break;
+                const KRec m = krec[members[C.first + C.acc[j]]];
+                double* mb = bins + 2 * local[C.first + C.acc[j]];
+                if ((m.meta >> 28) == MASK_PAIR) {
+                    const uint32_t q0 = mask_q(m.qpack, 0), q1 = mask_q(m.qpack, 1);
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) {
+                        const uint32_t r = base | tid | (k * nt);
+                        const uint32_t s = parity(r & m.zbase);
+                        const double pr = flip(acc_re[j][k], s);
+                        const double pi = flip(acc_im[j][k], s);
+                        const uint32_t idx = bit(r, q0) | (bit(r, q1) << 1);
+                        atomicAdd(&mb[2 * idx], pr);
+                        atomicAdd(&mb[2 * idx + 1], pi);
+                        for (uint32_t rb = r & ((1u << L.M) - 1u); rb; rb &= rb - 1) {
+                            const uint32_t c = __ffs(rb) - 1;
+                            atomicAdd(&mb[2 * (4 + 4 * c + idx)], pr);
+                            atomicAdd(&mb[2 * (4 + 4 * c + idx) + 1], pi);
+                        }
+                    }
+                } else {  // MASK_DIAG
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) {
+                        const uint32_t r = base | tid | (k * nt);
+                        for (int n = 0; n < L.n_diag; ++n) {
+                            const uint32_t s = parity(r & dz[n]);
+                            atomicAdd(&mb[2 * n], flip(acc_re[j][k], s));
+                            atomicAdd(&mb[2 * n + 1], flip(acc_im[j][k], s));
                         }
                     }
                 }
             }
         }
         __syncthreads();
-        for (uint32_t e = tid; e < 2 * C.bin_count; e += nt) mine[2 * (uint64_t)C.bin_begin + e] = bins[e];
+        // each member's bins to their place in this workgroup's slice
+        for (uint32_t j = C.first; j < C.first + C.count; ++j) {
+            const uint32_t lo = local[j];
+            const uint32_t hi = (j + 1 < C.first + C.count) ? local[j + 1] : C.bin_count;
+            const uint64_t go = krec[members[j]].pad[0];
+            for (uint32_t e = tid; e < 2 * (hi - lo); e += nt) mine[2 * go + e] = bins[2 * lo + e];
+        }
         __syncthreads();
     }
-    (void)kmask;
 }
 
 // out[i] += sum_b partial[b][i] for i < n (in block order b = 0, 1, ...).
@@ -205,26 +335,85 @@ __global__ void k_bins_reduce(const double* __restrict__ partial, int nblk, uint
 
 }  // namespace
 
-std::vector<GChunk> make_grad_chunks(const std::vector<MaskRec>& masks, const std::vector<uint64_t>& bin_off,
-                                     uint64_t n_bins, int tile_bits)
+GradChunks make_grad_chunks(const std::vector<MaskRec>& masks, const std::vector<uint64_t>& bin_off,
+                            uint64_t n_bins, int tile_bits, int lane_bits)
 {
-    std::vector<GChunk> out;
+    const uint32_t row_mask = (1u << tile_bits) - 1u;
+    const uint32_t lane_mask = (1u << lane_bits) - 1u;
+    const int kb = tile_bits - lane_bits;
+    if (kb < 0 || kb > kMaxKBits || lane_bits > 8) throw Error(SYK_EINVAL, "gradient: unsupported launch shape");
+    auto nbins = [&](uint32_t i) { return ((i + 1 < masks.size()) ? bin_off[i + 1] : n_bins) - bin_off[i]; };
+    struct Build {
+        GChunk c;
+        std::vector<uint32_t> mem;
+    };
+    std::vector<Build> near, far;
     for (uint32_t i = 0; i < (uint32_t)masks.size(); ++i) {
+        const uint32_t type = masks[i].type_tab >> 28;
         const uint32_t xh = masks[i].x >> tile_bits;
-        const uint64_t nb = ((i + 1 < masks.size()) ? bin_off[i + 1] : n_bins) - bin_off[i];
+        const uint64_t nb = nbins(i);
         if (nb > (uint64_t)kGradBinCap) throw Error(SYK_EUNSUPPORTED, "gradient: mask with too many bins");
-        const bool same = !out.empty() && out.back().x_high == xh;
-        if (!same || out.back().count == (uint32_t)kChunkMasks || out.back().bin_count + nb > (uint64_t)kGradBinCap) {
-            GChunk c{};
-            c.x_high = xh;
-            c.first = i;
-            c.bin_begin = (uint32_t)bin_off[i];
-            out.push_back(c);
+        const bool accm = type != MASK_QUAD;
+        const bool is_far = type != MASK_DIAG && (masks[i].x & row_mask) == 0u;
+        std::vector<Build>& out = is_far ? far : near;
+        const bool same = !out.empty() && (is_far || out.back().c.x_high == xh);
+        if (!same || out.back().c.count == (uint32_t)kChunkMasks ||
+            out.back().c.bin_count + nb > (uint64_t)kGradBinCap ||
+            (accm && out.back().c.n_acc == (uint32_t)kGradAccMasks)) {
+            Build b{};
+            b.c.x_high = is_far ? 0u : xh;
+            b.c.far = is_far ? 1u : 0u;
+            out.push_back(b);
         }
-        ++out.back().count;
-        out.back().bin_count += (uint32_t)nb;
+        Build& b = out.back();
+        if (accm) ++b.c.n_acc;
+        b.mem.push_back(i);
+        ++b.c.count;
+        b.c.bin_count += (uint32_t)nb;
     }
-    return out;
+    near.insert(near.end(), far.begin(), far.end());
+    GradChunks g;
+    for (Build& b : near) {
+        // near chunks: QUAD members by class, then PAIR / DIAG; far chunks keep mask order
+        auto key = [&](uint32_t i) {
+            const MaskRec& m = masks[i];
+            if ((m.type_tab >> 28) != MASK_QUAD) return 1000;
+            return b.c.far ? 0 : quad_class(m.x, m.zbase, lane_bits, kb);
+        };
+        std::stable_sort(b.mem.begin(), b.mem.end(), [&](uint32_t x, uint32_t y) { return key(x) < key(y); });
+        b.c.first = (uint32_t)g.members.size();
+        b.c.n_acc = 0;
+        uint32_t lo = 0;
+        for (uint32_t pos = 0; pos < b.mem.size(); ++pos) {
+            const uint32_t i = b.mem[pos];
+            const MaskRec& m = masks[i];
+            GRec r{};
+            if ((m.type_tab >> 28) == MASK_QUAD) {
+                ++b.c.n_quad;
+                if (!b.c.far) {
+                    const int cls = quad_class(m.x, m.zbase, lane_bits, kb);
+                    b.c.cnt[cls >> 2] += 1u << (8 * (cls & 3));
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t qb = mask_q(m.qpack, q);
+                        r.sel |= (qb < (uint32_t)lane_bits ? qb : 0x0cu) << (8 * q);
+                        const int kbit = (int)qb - lane_bits;
+                        if (kbit >= 0 && kbit < kb) r.koffs |= (1u << q) << (8 * kbit);
+                    }
+                    r.zl = m.zbase & lane_mask;
+                    r.xoff = m.x & lane_mask;
+                    r.koffs |= (m.x & 63u) << 24;
+                }
+            } else {
+                b.c.acc[b.c.n_acc++] = pos;
+            }
+            g.members.push_back(i);
+            g.local.push_back(lo);
+            g.grec.push_back(r);
+            lo += (uint32_t)nbins(i);
+        }
+        g.chunks.push_back(b.c);
+    }
+    return g;
 }
 
 void cheb_rec(syk_dtype dtype, int64_t n, void* out, const void* w, const void* y, const void* z, const void* x,
@@ -256,13 +445,21 @@ void grad_bins(syk_terms_s& h, const std::vector<const void*>& g, const std::vec
     const ApplyPlan P = plan_apply(H.M, 1, SYK_C128, &tune);
     require(P.nt <= 256, "gradient: launch shape");
     const KRec* krec = krecs_for(H, P);
+    // chunk records, member list, LDS bin offsets and QUAD member records in one device buffer
     auto it = h.grad_chunks.find(P.tile_bits);
     if (it == h.grad_chunks.end()) {
-        std::vector<GChunk> c = make_grad_chunks(T.masks, T.bin_off, T.n_bins, P.tile_bits);
+        const GradChunks c = make_grad_chunks(T.masks, T.bin_off, T.n_bins, P.tile_bits, P.lb);
+        const size_t cb = c.chunks.size() * sizeof(GChunk), mb = c.members.size() * sizeof(uint32_t);
+        const size_t gb = c.grec.size() * sizeof(GRec);
         std::unique_ptr<DevBuf> b(new DevBuf());
-        b->ensure(c.size() * sizeof(GChunk));
-        SYK_HIP(hipMemcpy(b->p, c.data(), c.size() * sizeof(GChunk), hipMemcpyHostToDevice));
-        h.grad_nchunks[P.tile_bits] = (int)c.size();
+        b->ensure(cb + gb + 2 * mb);
+        char* d = static_cast<char*>(b->p);
+        SYK_HIP(hipMemcpy(d, c.chunks.data(), cb, hipMemcpyHostToDevice));
+        SYK_HIP(hipMemcpy(d + cb, c.grec.data(), gb, hipMemcpyHostToDevice));
+        SYK_HIP(hipMemcpy(d + cb + gb, c.members.data(), mb, hipMemcpyHostToDevice));
+        SYK_HIP(hipMemcpy(d + cb + gb + mb, c.local.data(), mb, hipMemcpyHostToDevice));
+        h.grad_nchunks[P.tile_bits] = (int)c.chunks.size();
+        h.grad_nmembers[P.tile_bits] = (int)c.members.size();
         it = h.grad_chunks.emplace(P.tile_bits, std::move(b)).first;
     }
     GLayout L{};
@@ -273,7 +470,11 @@ void grad_bins(syk_terms_s& h, const std::vector<const void*>& g, const std::vec
     L.M = H.M;
     L.n_diag = H.n_diag;
     L.n_bins = T.n_bins;
+    // tile groups own the partial slices; chunk groups split each tile's
+    // chunks so that the grid fills the chip at small sizes
     const int nblk = (int)std::min<uint32_t>(L.n_tiles, 512u);
+    L.tile_groups = (uint32_t)nblk;
+    L.chunk_groups = (uint32_t)std::max(1, std::min(L.n_chunks, 2048 / nblk));
 
     // pointer lists and weights: one small synchronous upload
     std::vector<uint64_t> host(3 * (size_t)npairs);
@@ -291,13 +492,17 @@ void grad_bins(syk_terms_s& h, const std::vector<const void*>& g, const std::vec
     const double* wl = (const double*)(gl + 2 * npairs);
 
     double* partial = (double*)h.ws.get("grad_partial", (size_t)nblk * T.n_bins * 2 * sizeof(double));
-    const size_t lds = ((size_t)1 << P.tile_bits) * sizeof(c128) + (size_t)kGradBinCap * 2 * sizeof(double);
+    const size_t lds = ((size_t)1 << P.tile_bits) * sizeof(c128) + (size_t)kGradBinCap * 2 * sizeof(double) +
+                       (size_t)kChunkMasks * sizeof(uint32_t);
     const GChunk* chunks = it->second->as<GChunk>();
+    const GRec* grec = reinterpret_cast<const GRec*>(chunks + L.n_chunks);
+    const uint32_t* members = reinterpret_cast<const uint32_t*>(grec + h.grad_nmembers[P.tile_bits]);
+    const uint32_t* local = members + h.grad_nmembers[P.tile_bits];
     switch (P.rpt) {
-    case 1: hipLaunchKernelGGL(k_grad_bins<1>, dim3(nblk), dim3(P.nt), lds, st, krec, chunks, H.dz, L, gl, vl, wl, partial); break;
-    case 2: hipLaunchKernelGGL(k_grad_bins<2>, dim3(nblk), dim3(P.nt), lds, st, krec, chunks, H.dz, L, gl, vl, wl, partial); break;
-    case 4: hipLaunchKernelGGL(k_grad_bins<4>, dim3(nblk), dim3(P.nt), lds, st, krec, chunks, H.dz, L, gl, vl, wl, partial); break;
-    case 8: hipLaunchKernelGGL(k_grad_bins<8>, dim3(nblk), dim3(P.nt), lds, st, krec, chunks, H.dz, L, gl, vl, wl, partial); break;
+    case 1: hipLaunchKernelGGL(k_grad_bins<1>, dim3(nblk * L.chunk_groups), dim3(P.nt), lds, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, wl, partial); break;
+    case 2: hipLaunchKernelGGL(k_grad_bins<2>, dim3(nblk * L.chunk_groups), dim3(P.nt), lds, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, wl, partial); break;
+    case 4: hipLaunchKernelGGL(k_grad_bins<4>, dim3(nblk * L.chunk_groups), dim3(P.nt), lds, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, wl, partial); break;
+    case 8: hipLaunchKernelGGL(k_grad_bins<8>, dim3(nblk * L.chunk_groups), dim3(P.nt), lds, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, wl, partial); break;
     default: throw Error(SYK_EUNSUPPORTED, "gradient: launch shape");
     }
     SYK_HIP(hipGetLastError());

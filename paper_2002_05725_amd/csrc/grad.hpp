@@ -9,14 +9,39 @@
 namespace syk {
 
 constexpr int kGradBinCap = 2048;   // derivative bins of one chunk held in LDS
+constexpr int kGradAccMasks = 4;    // PAIR / DIAG masks of one chunk, summed over the pairs in registers
 
-// Masks sharing x >> tile_bits, cut so that their bins fit in LDS.
+// A chunk of masks whose bins are held in LDS together: members
+// [first, first + count) of the member list, at most kGradAccMasks of them PAIR
+// or DIAG masks (their positions in acc).  Masks of a near chunk share
+// x >> tile_bits (one staged source tile); their QUAD members come first,
+// sorted by row class (mask_classes.hpp) with cnt[] masks per class.  A far
+// chunk holds QUAD / PAIR masks that flip no row bit inside a tile, each
+// reading its own source tile straight from global memory.
 struct alignas(16) GChunk {
-    uint32_t x_high, first, count, bin_begin, bin_count, pad[3];
+    uint32_t x_high, first, count, bin_count, n_acc, far, n_quad, pad;
+    uint32_t acc[kGradAccMasks];
+    uint32_t cnt[8];   // QUAD members per class, one byte per class
+};
+static_assert(sizeof(GChunk) == 80, "GChunk layout");
+
+// Per-member record of a QUAD member of a near chunk.
+struct alignas(16) GRec {
+    uint32_t sel;    // byte selector gathering the lane bits of tid at q0..q3 (0x0c: not a lane bit)
+    uint32_t zl;     // lane bits of zbase
+    uint32_t xoff;   // x & lane mask: lane part of the source row
+    uint32_t koffs;  // byte b < 3: index bit set by k bit b (0 if not flipped); byte 3: in-wave lane bits of x
 };
 
-std::vector<GChunk> make_grad_chunks(const std::vector<MaskRec>& masks, const std::vector<uint64_t>& bin_off,
-                                     uint64_t n_bins, int tile_bits);
+struct GradChunks {
+    std::vector<GChunk> chunks;
+    std::vector<uint32_t> members;   // mask index of each member
+    std::vector<uint32_t> local;     // first LDS bin of each member
+    std::vector<GRec> grec;          // per member (zero for all but near QUAD members)
+};
+
+GradChunks make_grad_chunks(const std::vector<MaskRec>& masks, const std::vector<uint64_t>& bin_off,
+                            uint64_t n_bins, int tile_bits, int lane_bits);
 
 // out = b (w - gamma y) + s z + c x ; acc += ca out.  Null pointers drop their term.
 void cheb_rec(syk_dtype dtype, int64_t n, void* out, const void* w, const void* y, const void* z, const void* x,

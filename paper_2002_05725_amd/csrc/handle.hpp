@@ -71,7 +71,7 @@ struct syk_terms_s {
     syk::Workspace ws;
     unsigned upload_slot = 0;       // ring position of small coefficient uploads
     std::map<int, std::unique_ptr<syk::DevBuf>> grad_chunks;   // per tile_bits
-    std::map<int, int> grad_nchunks;
+    std::map<int, int> grad_nchunks, grad_nmembers;
     bool tuned = false;             // apply_H launch shape set by syk_set_apply_tuning
     int tune_tile_bits = 0, tune_threads = 0, tune_xcd = 1;
 };

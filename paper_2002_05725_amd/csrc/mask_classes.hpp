@@ -1,0 +1,56 @@
+// Row classes of QUAD masks, shared by the apply and gradient kernels.
+//
+// A thread owns the rows tid + (k << lane_bits) of a tile, k < 2^kb.  For each
+// of the kb k bits a QUAD mask either flips it, has it in its Z string, or
+// neither (flipped qubits are never in the Z string).  The class index has one
+// base-3 digit per k bit (1 = flipped, 2 = in the Z string); within a class
+// the source offset and the sign of every row are compile-time constants.
+#pragma once
+
+#include <utility>
+
+#include "terms.hpp"
+
+namespace syk {
+
+// Bits b < kb whose base-3 digit of cls equals digit.
+constexpr int class_bits(int cls, int kb, int digit)
+{
+    int r = 0;
+    for (int b = 0; b < kb; ++b) {
+        if (cls % 3 == digit) r |= 1 << b;
+        cls /= 3;
+    }
+    return r;
+}
+
+constexpr int ipow3(int n) { return n == 0 ? 1 : 3 * ipow3(n - 1); }
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+
+// Class of a QUAD mask for lane_bits lane bits and kb k bits.
+inline int quad_class(uint32_t x, uint32_t zbase, int lane_bits, int kb)
+{
+    int cls = 0, p3 = 1;
+    for (int b = 0; b < kb; ++b, p3 *= 3) {
+        const uint32_t q = (uint32_t)(lane_bits + b);
+        if ((x >> q) & 1u) cls += p3;
+        else if ((zbase >> q) & 1u) cls += 2 * p3;
+    }
+    return cls;
+}
+
+// Calls f(std::integral_constant<int, I>{}) for every I of the sequence.
+template <typename F, int... I>
+__device__ __forceinline__ void for_each_class(F& f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+
+// Sign flip by a word whose bit 31 is the sign to apply (other bits zero).
+__device__ __forceinline__ double flip31(double x, uint32_t s)
+{
+    return __hiloint2double(__double2hiint(x) ^ (int)s, __double2loint(x));
+}
+__device__ __forceinline__ float flip31(float x, uint32_t s) { return __int_as_float(__float_as_int(x) ^ (int)s); }
+
+}  // namespace syk
