@@ -133,8 +133,9 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
     const uint32_t nt = blockDim.x;
     const uint32_t lb = 31u - __clz(nt);                              // lane bits (8 when RPT > 1)
     const uint32_t tile_elems = nt * RPT;
-    c128* src = reinterpret_cast<c128*>(smem_raw);
-    double* bins = reinterpret_cast<double*>(src + tile_elems);     // [kGradBinCap][2]
+    constexpr int PP = kGradPairsPerStage;
+    c128* src = reinterpret_cast<c128*>(smem_raw);                  // [PP][tile_elems]
+    double* bins = reinterpret_cast<double*>(src + PP * tile_elems);   // [kGradBinCap][2]
     uint32_t* fold = reinterpret_cast<uint32_t*>(bins + 2 * kGradBinCap);   // [kChunkMasks]
     const uint32_t tid = threadIdx.x;
     // bits 0..3 and 4..7 of tid, one per byte (table-index gather)
@@ -168,28 +169,42 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
 #pragma unroll
                 for (int k = 0; k < RPT; ++k) acc_re[j][k] = acc_im[j][k] = 0.0;
 
-            for (int p = 0; p < L.npairs; ++p) {
-                const c128* __restrict__ g = gs[p];
-                const c128* __restrict__ v = vs[p];
-                const double wt = wts[p];
-                c128 gk[RPT];   // w_p g_p on the thread's rows
+            // PP pairs at a time (the host pads the list with zero-weight pairs)
+            for (int p0 = 0; p0 < L.npairs; p0 += PP) {
+                c128 gk[PP][RPT];   // w_p g_p on the thread's rows
 #pragma unroll
-                for (int k = 0; k < RPT; ++k) {
-                    gk[k] = g[base + tid + k * nt];
-                    gk[k].re *= wt;
-                    gk[k].im *= wt;
+                for (int u = 0; u < PP; ++u) {
+                    const c128* __restrict__ g = gs[p0 + u];
+                    const double wt = wts[p0 + u];
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) {
+                        gk[u][k] = g[base + tid + k * nt];
+                        gk[u][k].re *= wt;
+                        gk[u][k].im *= wt;
+                    }
                 }
                 if (!C.far) {
                     __syncthreads();   // previous users of src are done
                     const uint64_t sbase = (uint64_t)(tile ^ C.x_high) << L.tile_bits;
 #pragma unroll
-                    for (int k = 0; k < RPT; ++k) src[tid + k * nt] = v[sbase + tid + k * nt];
+                    for (int u = 0; u < PP; ++u) {
+                        const c128* __restrict__ v = vs[p0 + u];
+#pragma unroll
+                        for (int k = 0; k < RPT; ++k) src[u * tile_elems + tid + k * nt] = v[sbase + tid + k * nt];
+                    }
                     __syncthreads();
                 }
-                // source row k of a mask: staged tile, or (far chunks) the mask's own tile
-                auto source = [&](const KRec& m, int k) -> c128 {
-                    if (C.far) return v[((uint64_t)(tile ^ m.pad[1]) << L.tile_bits) + tid + k * nt];
-                    return src[(tid + k * nt) ^ m.xl];
+                // sum over the staged pairs of w_p conj(g_p) x_p for source row k of a mask:
+                // the staged tiles, or (far chunks) the mask's own tile
+                auto product = [&](const KRec& m, int k, double& pr, double& pi) {
+                    pr = pi = 0.0;
+#pragma unroll
+                    for (int u = 0; u < PP; ++u) {
+                        const c128 x = C.far ? vs[p0 + u][((uint64_t)(tile ^ m.pad[1]) << L.tile_bits) + tid + k * nt]
+                                             : src[u * tile_elems + ((tid + k * nt) ^ m.xl)];
+                        pr += gk[u][k].re * x.re + gk[u][k].im * x.im;
+                        pi += gk[u][k].re * x.im - gk[u][k].im * x.re;
+                    }
                 };
 
                 if (C.far) {
@@ -200,9 +215,10 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
                         double ar = 0.0, ai = 0.0;
 #pragma unroll
                         for (int k = 0; k < RPT; ++k) {
-                            const c128 x = source(m, k);
-                            ar += gk[k].re * x.re + gk[k].im * x.im;
-                            ai += gk[k].re * x.im - gk[k].im * x.re;
+                            double pr, pi;
+                            product(m, k, pr, pi);
+                            ar += pr;
+                            ai += pi;
                         }
                         const uint32_t s = parity(base & m.zbase);
                         ar = group_sum(flip(ar, s), 0u);
@@ -236,10 +252,14 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
                             const uint32_t sb = tid ^ q.xoff;
 #pragma unroll
                             for (int k = 0; k < RPT; ++k) {
-                                const c128 x = src[sb + (((uint32_t)k ^ XK) << lb)];
+                                double pr = 0.0, pi = 0.0;
+#pragma unroll
+                                for (int u = 0; u < PP; ++u) {
+                                    const c128 x = src[u * tile_elems + sb + (((uint32_t)k ^ XK) << lb)];
+                                    pr += gk[u][k].re * x.re + gk[u][k].im * x.im;
+                                    pi += gk[u][k].re * x.im - gk[u][k].im * x.re;
+                                }
                                 const bool neg = (__builtin_popcount((uint32_t)k & ZK) & 1) != 0;
-                                const double pr = gk[k].re * x.re + gk[k].im * x.im;
-                                const double pi = gk[k].re * x.im - gk[k].im * x.re;
                                 er[k & (int)XK] += neg ? -pr : pr;
                                 ei[k & (int)XK] += neg ? -pi : pi;
                             }
@@ -268,9 +288,10 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
                     const KRec ma = krec[members[C.first + C.acc[j]]];
 #pragma unroll
                     for (int k = 0; k < RPT; ++k) {
-                        const c128 x = source(ma, k);
-                        acc_re[j][k] += gk[k].re * x.re + gk[k].im * x.im;
-                        acc_im[j][k] += gk[k].re * x.im - gk[k].im * x.re;
+                        double pr, pi;
+                        product(ma, k, pr, pi);
+                        acc_re[j][k] += pr;
+                        acc_im[j][k] += pi;
                     }
                 }
             }
@@ -466,7 +487,6 @@ void grad_bins(syk_terms_s& h, const std::vector<const void*>& g, const std::vec
     L.tile_bits = P.tile_bits;
     L.n_tiles = (uint32_t)(((uint64_t)1 << H.M) >> P.tile_bits);
     L.n_chunks = h.grad_nchunks[P.tile_bits];
-    L.npairs = npairs;
     L.M = H.M;
     L.n_diag = H.n_diag;
     L.n_bins = T.n_bins;
@@ -476,24 +496,29 @@ void grad_bins(syk_terms_s& h, const std::vector<const void*>& g, const std::vec
     L.tile_groups = (uint32_t)nblk;
     L.chunk_groups = (uint32_t)std::max(1, std::min(L.n_chunks, 2048 / nblk));
 
-    // pointer lists and weights: one small synchronous upload
-    std::vector<uint64_t> host(3 * (size_t)npairs);
-    for (int p = 0; p < npairs; ++p) {
-        host[p] = (uint64_t)(uintptr_t)g[p];
-        host[npairs + p] = (uint64_t)(uintptr_t)v[p];
-        double wp = w[p];
-        std::memcpy(&host[2 * npairs + p], &wp, sizeof(double));
+    // pointer lists and weights: one small synchronous upload.  The list is
+    // padded to a multiple of kGradPairsPerStage with copies of pair 0 of
+    // weight 0 (their products are exact zeros).
+    const int np = (npairs + kGradPairsPerStage - 1) / kGradPairsPerStage * kGradPairsPerStage;
+    L.npairs = np;
+    std::vector<uint64_t> host(3 * (size_t)np);
+    for (int p = 0; p < np; ++p) {
+        const int q = p < npairs ? p : 0;
+        host[p] = (uint64_t)(uintptr_t)g[q];
+        host[np + p] = (uint64_t)(uintptr_t)v[q];
+        double wp = p < npairs ? w[p] : 0.0;
+        std::memcpy(&host[2 * np + p], &wp, sizeof(double));
     }
     void* dlist = h.ws.get("grad_lists", host.size() * sizeof(uint64_t));
     SYK_HIP(hipMemcpyAsync(dlist, host.data(), host.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
     SYK_HIP(hipStreamSynchronize(st));
     const c128* const* gl = (const c128* const*)dlist;
-    const c128* const* vl = gl + npairs;
-    const double* wl = (const double*)(gl + 2 * npairs);
+    const c128* const* vl = gl + np;
+    const double* wl = (const double*)(gl + 2 * np);
 
     double* partial = (double*)h.ws.get("grad_partial", (size_t)nblk * T.n_bins * 2 * sizeof(double));
-    const size_t lds = ((size_t)1 << P.tile_bits) * sizeof(c128) + (size_t)kGradBinCap * 2 * sizeof(double) +
-                       (size_t)kChunkMasks * sizeof(uint32_t);
+    const size_t lds = (size_t)kGradPairsPerStage * ((size_t)1 << P.tile_bits) * sizeof(c128) +
+                       (size_t)kGradBinCap * 2 * sizeof(double) + (size_t)kChunkMasks * sizeof(uint32_t);
     const GChunk* chunks = it->second->as<GChunk>();
     const GRec* grec = reinterpret_cast<const GRec*>(chunks + L.n_chunks);
     const uint32_t* members = reinterpret_cast<const uint32_t*>(grec + h.grad_nmembers[P.tile_bits]);

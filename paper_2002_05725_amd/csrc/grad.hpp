@@ -8,8 +8,9 @@
 
 namespace syk {
 
-constexpr int kGradBinCap = 2048;   // derivative bins of one chunk held in LDS
-constexpr int kGradAccMasks = 4;    // PAIR / DIAG masks of one chunk, summed over the pairs in registers
+constexpr int kGradBinCap = 1024;   // derivative bins of one chunk held in LDS
+constexpr int kGradAccMasks = 2;    // PAIR / DIAG masks of one chunk, summed over the pairs in registers
+constexpr int kGradPairsPerStage = 2;   // (g, v) pairs whose source tiles are staged together
 
 // A chunk of masks whose bins are held in LDS together: members
 // [first, first + count) of the member list, at most kGradAccMasks of them PAIR
