@@ -116,3 +116,64 @@ def two_point_trace(dense_exp, chis, i: int, beta: float, times):
         U = dense_exp.matrix(-1j * t)
         out[n] = np.trace(U.conj().T @ chis[i] @ U @ chis[i] @ rho) / Zt
     return out
+
+
+# ---------------------------------------------------------------------------
+# Unregularized OTOC (SI section "Unregularized OTOCs"):
+#     F_u(t) = <chi_i(t) chi_j chi_i(t) chi_j rho> = Tr[W V W V rho] / Tr rho,
+# W = chi_i(t), V = chi_j.  Symmetric cut of the trace with phi = rho^{1/2} psi:
+#     F_u_est = <phi| W V W V |phi> / <phi|phi> = <V W phi | W V phi> / <phi|phi>
+# (W and V are Hermitian).  Complex in general; both parts are returned.
+def otoc_u_estimator(prop, maj, psi, i: int, j: int, beta: float, times):
+    """F_u estimate for each t (each time propagated from scratch).
+    Returns (Re F_u, Im F_u, Z)."""
+    phi = prop.imag(psi, beta / 2)
+    Z = float(np.vdot(phi, phi).real)
+    F = np.empty(len(times))
+    Fi = np.empty(len(times))
+    for n, t in enumerate(times):
+        wv = prop.real(maj(i, prop.real(maj(j, phi), t)), -t)      # W V phi
+        vw = maj(j, prop.real(maj(i, prop.real(phi, t)), -t))      # V W phi
+        val = np.vdot(vw, wv) / Z
+        F[n], Fi[n] = val.real, val.imag
+    return F, Fi, Z
+
+
+def otoc_u_trace(dense_exp, chis, i: int, j: int, beta: float, times):
+    """Exact F_u(t) = Tr[W(t) V W(t) V rho] / Tr rho (complex)."""
+    rho = dense_exp.matrix(-beta)
+    Zt = float(np.trace(rho).real)
+    out = np.empty(len(times), dtype=np.complex128)
+    for n, t in enumerate(times):
+        U = dense_exp.matrix(-1j * t)
+        Wt = U.conj().T @ chis[i] @ U
+        out[n] = np.trace(Wt @ chis[j] @ Wt @ chis[j] @ rho) / Zt
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Imaginary-time Green's function (main text Eq. 2):
+#     G(tau) = <chi_i(tau) chi_i(0)>_beta,  chi(tau) = e^{tau H} chi e^{-tau H},
+# 0 <= tau <= beta.  Tr[e^{-(beta - tau) H} chi e^{-tau H} chi] cut
+# symmetrically around the typical state: with u = e^{-(beta - tau) H / 2} psi,
+#     G_est(tau) = || e^{-tau H / 2} chi_i u ||^2 / || e^{-beta H / 2} psi ||^2.
+def imag_two_point_estimator(prop, maj, psi, i: int, beta: float, taus):
+    """G_est(tau) for each tau (each propagated from scratch).  Returns (G, Z)."""
+    Z = float(np.linalg.norm(prop.imag(psi, beta / 2)) ** 2)
+    out = np.empty(len(taus))
+    for n, tau in enumerate(taus):
+        u = prop.imag(psi, (beta - tau) / 2)
+        w = prop.imag(maj(i, u), tau / 2)
+        out[n] = float(np.vdot(w, w).real) / Z
+    return out, Z
+
+
+def imag_two_point_trace(dense_exp, chis, i: int, beta: float, taus):
+    """Exact G(tau) = Tr[e^{tau H} chi_i e^{-tau H} chi_i rho] / Tr rho."""
+    rho = dense_exp.matrix(-beta)
+    Zt = float(np.trace(rho).real)
+    out = np.empty(len(taus))
+    for n, tau in enumerate(taus):
+        Xt = dense_exp.matrix(tau) @ chis[i] @ dense_exp.matrix(-tau)
+        out[n] = float(np.trace(Xt @ chis[i] @ rho).real) / Zt
+    return out

@@ -329,3 +329,77 @@ def test_chebyshev_tangent_euler_identity():
     dFdb = (F(beta + d, t) - F(beta - d, t)) / (2 * d)
     dFdt = (F(beta, t + d) - F(beta, t - d)) / (2 * d)
     assert abs(np.dot(J, g) - (beta * dFdb + t * dFdt)) < 1e-8
+
+
+# ------------------------------------- unregularized OTOC and imaginary-time G
+def _golden_n4_unreg_imag():
+    return np.loadtxt(os.path.join(GOLDEN, "n4_unreg_imag.txt"))
+
+
+def test_n4_unreg_otoc_and_imag_two_point_closed_form():
+    """Exact-trace F_u(t) and G(tau) at N=4 against tests/golden/n4_unreg_imag.*"""
+    chis = jw.dense_majoranas(4)
+    for Jv, beta, s, reF, imF, G in _golden_n4_unreg_imag():
+        E = krylov.DenseExp(jw.dense_H(4, np.array([Jv])))
+        Fu = correlators.otoc_u_trace(E, chis, 0, 1, beta, [s])[0]
+        assert abs(Fu - (reF + 1j * imF)) < 1e-14
+        if s <= beta:
+            assert abs(correlators.imag_two_point_trace(E, chis, 0, beta, [s])[0] - G) < 1e-14
+
+
+@pytest.mark.parametrize("N,beta", [(4, 1.5), (8, 0.0), (8, 2.5)])
+def test_unreg_and_imag_estimators_basis_sum_is_trace(N, beta):
+    """Summed over an orthonormal basis, the numerators of F_u_est and G_est
+    give Tr[W V W V rho] and Tr[e^{-(beta-tau)H} chi e^{-tau H} chi]; the
+    denominators give Tr rho.  A misplaced half of rho or a swapped W, V
+    breaks it."""
+    J = inputs.couplings(N, 3) if N > 4 else np.array([1.1])
+    H = jw.dense_H(N, J)
+    E = krylov.DenseExp(H)
+    chis = jw.dense_majoranas(N)
+    ex = correlators.ExactPropagator(E)
+    maj = lambda a, v: jw.majorana_apply(N, a, v)
+    D = H.shape[0]
+    times = [0.0, 0.7, 2.0]
+    taus = [0.0, 0.3 * beta, beta]
+    nF = np.zeros(len(times), complex)
+    nG = np.zeros(len(taus))
+    den = 0.0
+    for r in range(D):
+        e = np.zeros(D, complex)
+        e[r] = 1.0
+        F, Fi, Z = correlators.otoc_u_estimator(ex, maj, e, 0, 1, beta, times)
+        G, Z2 = correlators.imag_two_point_estimator(ex, maj, e, 0, beta, taus)
+        nF += (F + 1j * Fi) * Z
+        nG += G * Z2
+        den += Z
+    assert np.abs(nF / den - correlators.otoc_u_trace(E, chis, 0, 1, beta, times)).max() < 1e-13
+    assert np.abs(nG / den - correlators.imag_two_point_trace(E, chis, 0, beta, taus)).max() < 1e-13
+
+
+def test_unreg_otoc_and_imag_two_point_identities():
+    """Identities that hold state by state or for the exact trace:
+    F_u(0) = -1/4 (chi_i chi_j chi_i chi_j = -1/4); G_est(0) = 1/2 (chi^2 = 1/2);
+    at beta = 0 F_u equals the regularized F; the exact G obeys G(tau) = G(beta - tau)."""
+    N = 8
+    J = inputs.couplings(N, 5)
+    H = jw.dense_H(N, J)
+    E = krylov.DenseExp(H)
+    chis = jw.dense_majoranas(N)
+    ex = correlators.ExactPropagator(E)
+    maj = lambda a, v: jw.majorana_apply(N, a, v)
+    psi = inputs.typical_state(N, 7)
+    F, Fi, _ = correlators.otoc_u_estimator(ex, maj, psi, 2, 5, 3.0, [0.0])
+    assert abs(F[0] + 0.25) < 1e-14 and abs(Fi[0]) < 1e-14
+    G, _ = correlators.imag_two_point_estimator(ex, maj, psi, 3, 4.0, [0.0])
+    assert abs(G[0] - 0.5) < 1e-14
+    times = [0.4, 1.3, 2.9]
+    Fu0 = correlators.otoc_u_trace(E, chis, 0, 1, 0.0, times)
+    Fr0 = correlators.otoc_trace(E, chis, 0, 1, 0.0, times)
+    assert np.abs(Fu0.real - Fr0).max() < 1e-13
+    beta = 2.6
+    taus = np.array([0.0, 0.4, 1.1, 1.3])
+    Gt = correlators.imag_two_point_trace(E, chis, 1, beta, taus)
+    Gb = correlators.imag_two_point_trace(E, chis, 1, beta, beta - taus)
+    assert np.abs(Gt - Gb).max() < 1e-13
+    assert abs(Gt[0] - 0.5) < 1e-14
