@@ -174,6 +174,34 @@ syk_status syk_otoc(syk_terms t, syk_dtype dtype, int i, int j, double beta, con
                     hipStream_t stream);
 
 /*
+ * Unregularized OTOC (SI section "Unregularized OTOCs") from a typical state,
+ * i != j:
+ *   F_u(t) = Tr[W V W V rho] / Tr rho,  W = chi_i(t), V = chi_j, rho = e^{-beta H},
+ * with the trace cut symmetrically around psi: <V W phi | W V phi> / <phi|phi>,
+ * phi = rho^{1/2} psi.  Forward legs advance incrementally between output times;
+ * each output time propagates back by its full t.  Same arguments and layouts
+ * as syk_otoc: F [nt][nvec] the real part, F_im (may be NULL) the imaginary
+ * part (nonzero in general), Z [nvec] or NULL.
+ */
+syk_status syk_otoc_unregularized(syk_terms t, syk_dtype dtype, int i, int j, double beta, const double* times,
+                                  int nt, int nvec, const int32_t* real_of_col, const void* psi0,
+                                  const syk_krylov_opts* opts, double* F, double* F_im, double* Z,
+                                  hipStream_t stream);
+
+/*
+ * Imaginary-time Green's function (main text Eq. 2) from a typical state:
+ *   G(tau) = <chi_i(tau) chi_i>_beta,  chi(tau) = e^{tau H} chi e^{-tau H},
+ * estimated as ||e^{-tau H/2} chi_i e^{-(beta - tau) H/2} psi||^2 / <psi|rho|psi>
+ * (real, G(0) = 1/2).  taus: host, ntau >= 1 ascending values in [0, beta]
+ * (processed from the largest down, so e^{-(beta - tau) H/2} psi advances
+ * incrementally).  psi0: device, nvec columns.  G: host [ntau][nvec];
+ * Z: host [nvec] or NULL.  Imaginary legs use opts->tau_step.
+ */
+syk_status syk_imag_two_point(syk_terms t, syk_dtype dtype, int i, double beta, const double* taus, int ntau,
+                              int nvec, const int32_t* real_of_col, const void* psi0, const syk_krylov_opts* opts,
+                              double* G, double* Z, hipStream_t stream);
+
+/*
  * Smallest and largest Ritz values of m Lanczos steps started from psi0
  * (device, one column): inner bounds on the spectrum of realisation 0 that
  * converge quickly at the edges.  Used to choose the Chebyshev interval; e_min

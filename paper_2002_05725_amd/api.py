@@ -202,6 +202,44 @@ def otoc(terms: Terms, i: int, j: int, beta: float, times, psi0: torch.Tensor, m
     return F, Fi, Z
 
 
+def otoc_unregularized(terms: Terms, i: int, j: int, beta: float, times, psi0: torch.Tensor, m: int = 20,
+                       dt: float = 0.1, tau_step: float = 0.1, tol: float = 0.0, real_of_col=None):
+    """Unregularized OTOC: Re F_u ([nt, nvec]), Im F_u ([nt, nvec]) and Z ([nvec]);
+    see syk_otoc_unregularized."""
+    _check_state(psi0, terms.dim, "psi0")
+    nvec = _nvec(psi0)
+    t = np.ascontiguousarray(times, dtype=np.float64)
+    F = np.empty((t.size, nvec))
+    Fi = np.empty((t.size, nvec))
+    Z = np.empty(nvec)
+    ra, rp = _real_arr(real_of_col, nvec)
+    o = _opts(m, dt, tau_step, tol)
+    check(lib().syk_otoc_unregularized(terms.handle, _dtype_code(psi0), int(i), int(j), float(beta),
+                                       t.ctypes.data_as(ctypes.c_void_p), t.size, nvec, rp,
+                                       ctypes.c_void_p(psi0.data_ptr()), ctypes.byref(o),
+                                       F.ctypes.data_as(ctypes.c_void_p), Fi.ctypes.data_as(ctypes.c_void_p),
+                                       Z.ctypes.data_as(ctypes.c_void_p), _stream()), "syk_otoc_unregularized")
+    return F, Fi, Z
+
+
+def imag_two_point(terms: Terms, i: int, beta: float, taus, psi0: torch.Tensor, m: int = 20, tau_step: float = 0.1,
+                   real_of_col=None):
+    """G(tau) ([ntau, nvec], real) and Z ([nvec]); see syk_imag_two_point."""
+    _check_state(psi0, terms.dim, "psi0")
+    nvec = _nvec(psi0)
+    tau = np.ascontiguousarray(taus, dtype=np.float64)
+    G = np.empty((tau.size, nvec))
+    Z = np.empty(nvec)
+    ra, rp = _real_arr(real_of_col, nvec)
+    o = _opts(m, 0.1, tau_step, 0.0)
+    check(lib().syk_imag_two_point(terms.handle, _dtype_code(psi0), int(i), float(beta),
+                                   tau.ctypes.data_as(ctypes.c_void_p), tau.size, nvec, rp,
+                                   ctypes.c_void_p(psi0.data_ptr()), ctypes.byref(o),
+                                   G.ctypes.data_as(ctypes.c_void_p), Z.ctypes.data_as(ctypes.c_void_p), _stream()),
+          "syk_imag_two_point")
+    return G, Z
+
+
 def spectrum_bounds(terms: Terms, psi0: torch.Tensor, m: int = 40):
     """(e_min, e_max): extreme Ritz values of m Lanczos steps from psi0."""
     _check_state(psi0, terms.dim, "psi0")

@@ -366,6 +366,44 @@ syk_status syk_otoc(syk_terms t, syk_dtype dtype, int i, int j, double beta, con
     });
 }
 
+syk_status syk_otoc_unregularized(syk_terms t, syk_dtype dtype, int i, int j, double beta, const double* times,
+                                  int nt, int nvec, const int32_t* real_of_col, const void* psi0,
+                                  const syk_krylov_opts* opts, double* F, double* F_im, double* Z,
+                                  hipStream_t stream)
+{
+    return guard([&] {
+        check_handle(t);
+        check_dtype(dtype);
+        check_block(t, nvec, real_of_col);
+        syk_krylov_opts o = check_opts(opts);
+        require(i >= 0 && i < t->H.N && j >= 0 && j < t->H.N, "Majorana index out of range");
+        require(i != j, "the OTOC needs i != j");
+        require(std::isfinite(beta) && beta >= 0, "beta must be finite and >= 0");
+        check_ptr(psi0, "psi0");
+        require(F != nullptr, "F is NULL");
+        BlockCtx c(*t, dtype, nvec, real_of_col, stream);
+        otoc_unregularized(c, i, j, beta, times, nt, psi0, o, F, F_im, Z);
+    });
+}
+
+syk_status syk_imag_two_point(syk_terms t, syk_dtype dtype, int i, double beta, const double* taus, int ntau,
+                              int nvec, const int32_t* real_of_col, const void* psi0, const syk_krylov_opts* opts,
+                              double* G, double* Z, hipStream_t stream)
+{
+    return guard([&] {
+        check_handle(t);
+        check_dtype(dtype);
+        check_block(t, nvec, real_of_col);
+        syk_krylov_opts o = check_opts(opts);
+        require(i >= 0 && i < t->H.N, "Majorana index out of range");
+        require(std::isfinite(beta) && beta >= 0, "beta must be finite and >= 0");
+        check_ptr(psi0, "psi0");
+        require(G != nullptr, "G is NULL");
+        BlockCtx c(*t, dtype, nvec, real_of_col, stream);
+        imag_two_point(c, i, beta, taus, ntau, psi0, o, G, Z);
+    });
+}
+
 syk_status syk_spectrum_bounds(syk_terms t, syk_dtype dtype, int m, const void* psi0, double* e_min, double* e_max,
                                hipStream_t stream)
 {

@@ -1,6 +1,7 @@
-// Typical-state estimators of the two-point function (main text Eq. 2-3) and
-// the regularized OTOC (main text Eq. 4), with the trace replaced by a
-// Gaussian random state as in the SI section "Disorder averaging".
+// Typical-state estimators of the two-point functions (main text Eq. 2-3), the
+// regularized OTOC (main text Eq. 4) and the unregularized OTOC (SI section
+// "Unregularized OTOCs"), with the trace replaced by a Gaussian random state
+// as in the SI section "Disorder averaging".
 #include "estimators.hpp"
 
 #include <cmath>
@@ -95,6 +96,82 @@ void otoc(BlockCtx& c, int i, int j, double beta, const double* t, int nt, const
             F[(size_t)k * B + col] = d[col].real() / z[col];
             if (F_im) F_im[(size_t)k * B + col] = d[col].imag() / z[col];
         }
+    }
+    if (Z)
+        for (int col = 0; col < B; ++col) Z[col] = z[col];
+    if (o.tol > 0)
+        for (double e : st.err)
+            if (e > o.tol) throw Error(SYK_ENOTCONVERGED, "Krylov error estimate above tolerance");
+}
+
+void otoc_unregularized(BlockCtx& c, int i, int j, double beta, const double* t, int nt, const void* psi0,
+                        const syk_krylov_opts& o, double* F, double* F_im, double* Z)
+{
+    check_times(t, nt);
+    const int B = c.nvec;
+    const size_t vb = c.ops.vec_bytes();
+    void* uphi = c.h.ws.get("est_a", vb);   // U(t) phi, phi = rho^{1/2} psi
+    void* uvp = c.h.ws.get("est_b", vb);    // U(t) V phi
+    void* x = c.h.ws.get("est_x", vb);
+    void* y = c.h.ws.get("est_y", vb);
+    void* y2 = c.h.ws.get("est_tmp", vb);
+    KrylovStats st;
+
+    c.ops.copy(uphi, psi0);
+    krylov_propagate(c, uphi, kImag, beta / 2, o.tau_step, o.m, st);
+    const std::vector<double> z = c.ops.norm2(uphi);                           // <psi|rho|psi>
+    c.ops.majorana(j, uphi, uvp);
+
+    double tcur = 0.0;
+    for (int k = 0; k < nt; ++k) {
+        krylov_propagate(c, uphi, kReal, t[k] - tcur, o.dt, o.m, st);
+        krylov_propagate(c, uvp, kReal, t[k] - tcur, o.dt, o.m, st);
+        tcur = t[k];
+        // W V phi = U^dag chi_i U [V phi]
+        c.ops.majorana(i, uvp, x);
+        krylov_propagate(c, x, std::conj(kReal), t[k], o.dt, o.m, st);
+        // V W phi = chi_j U^dag chi_i U [phi]
+        c.ops.majorana(i, uphi, y);
+        krylov_propagate(c, y, std::conj(kReal), t[k], o.dt, o.m, st);
+        c.ops.majorana(j, y, y2);
+        std::vector<zd> d = c.ops.multidot(y2, 1, x);                           // <V W phi | W V phi>
+        for (int col = 0; col < B; ++col) {
+            F[(size_t)k * B + col] = d[col].real() / z[col];
+            if (F_im) F_im[(size_t)k * B + col] = d[col].imag() / z[col];
+        }
+    }
+    if (Z)
+        for (int col = 0; col < B; ++col) Z[col] = z[col];
+    if (o.tol > 0)
+        for (double e : st.err)
+            if (e > o.tol) throw Error(SYK_ENOTCONVERGED, "Krylov error estimate above tolerance");
+}
+
+void imag_two_point(BlockCtx& c, int i, double beta, const double* tau, int ntau, const void* psi0,
+                    const syk_krylov_opts& o, double* G, double* Z)
+{
+    check_times(tau, ntau);
+    require(tau[ntau - 1] <= beta, "imaginary times must lie in [0, beta]");
+    const int B = c.nvec;
+    const size_t vb = c.ops.vec_bytes();
+    void* u = c.h.ws.get("est_a", vb);      // e^{-(beta - tau) H / 2} psi, tau descending
+    void* w = c.h.ws.get("est_b", vb);
+    KrylovStats st;
+
+    c.ops.copy(w, psi0);
+    krylov_propagate(c, w, kImag, beta / 2, o.tau_step, o.m, st);
+    const std::vector<double> z = c.ops.norm2(w);                              // <psi|rho|psi>
+
+    c.ops.copy(u, psi0);
+    double done = 0.0;   // imaginary time already applied to u
+    for (int k = ntau - 1; k >= 0; --k) {
+        const double need = (beta - tau[k]) / 2;
+        krylov_propagate(c, u, kImag, need - done, o.tau_step, o.m, st);
+        done = need;
+        c.ops.majorana(i, u, w);
+        krylov_propagate(c, w, kImag, tau[k] / 2, o.tau_step, o.m, st);
+        const std::vector<double> n2 = c.ops.norm2(w);
+        for (int col = 0; col < B; ++col) G[(size_t)k * B + col] = n2[col] / z[col];
     }
     if (Z)
         for (int col = 0; col < B; ++col) Z[col] = z[col];

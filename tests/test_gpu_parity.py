@@ -184,6 +184,61 @@ def test_otoc_vs_exact_small(N, beta):
         assert abs(F[0, 0] + 0.25) <= 1e-13
 
 
+@pytest.mark.parametrize("N,beta", [(12, 0.0), (12, 6.0), (16, 3.0)])
+def test_otoc_unregularized_vs_exact_small(N, beta):
+    """Unregularized OTOC (real and imaginary parts) against the checker's
+    estimator with exact exponentials on the same state."""
+    J = inputs.couplings(N, 0)
+    psi = inputs.typical_state(N, 1)
+    times = [0.0, 0.5, 1.5, 3.0]
+    T = api.Terms(N, J)
+    F, Fi, Z = api.otoc_unregularized(T, 0, 1, beta, times, _gpu(psi), m=20, dt=0.25, tau_step=0.25)
+    E = krylov.DenseExp(jw.dense_H(N, J))
+    maj = lambda a, v: jw.majorana_apply(N, a, v)
+    Fr, Fir, Zr = correlators.otoc_u_estimator(correlators.ExactPropagator(E), maj, psi, 0, 1, beta, times)
+    scale = np.abs(Fr + 1j * Fir).max()
+    assert np.abs(F[:, 0] - Fr).max() <= 1e-10 * scale
+    assert np.abs(Fi[:, 0] - Fir).max() <= 1e-10 * scale
+    assert abs(Z[0] - Zr) <= 1e-10 * Zr
+    assert abs(F[0, 0] + 0.25) <= 1e-13 and abs(Fi[0, 0]) <= 1e-13
+
+
+@pytest.mark.parametrize("N,beta", [(12, 4.0), (16, 10.0)])
+def test_imag_two_point_vs_exact_small(N, beta):
+    """G(tau) on [0, beta] against the checker's estimator with exact exponentials."""
+    J = inputs.couplings(N, 0)
+    psi = inputs.typical_state(N, 1)
+    taus = np.linspace(0.0, beta, 6)
+    T = api.Terms(N, J)
+    G, Z = api.imag_two_point(T, 3, beta, taus, _gpu(psi), m=20, tau_step=0.25)
+    E = krylov.DenseExp(jw.dense_H(N, J))
+    maj = lambda a, v: jw.majorana_apply(N, a, v)
+    Gr, Zr = correlators.imag_two_point_estimator(correlators.ExactPropagator(E), maj, psi, 3, beta, taus)
+    assert np.abs(G[:, 0] - Gr).max() <= 1e-10 * np.abs(Gr).max()
+    assert abs(Z[0] - Zr) <= 1e-10 * Zr
+    assert abs(G[0, 0] - 0.5) <= 1e-13
+
+
+def test_unregularized_and_imag_blocks_match_columns():
+    """Block calls (two realisations, two states each) equal the single-column calls."""
+    N = 20
+    Js = np.stack([inputs.couplings(N, inputs.batch_coupling_seed(N, r)) for r in range(2)])
+    T = api.Terms(N, Js)
+    host = np.stack([inputs.typical_state(N, inputs.batch_state_seed(N, r, s)) for r in range(2) for s in range(2)])
+    real = [0, 0, 1, 1]
+    times, taus = [0.0, 0.7, 1.6], [0.0, 1.0, 2.5]
+    Fb, Fib, _ = api.otoc_unregularized(T, 2, 5, 2.5, times, _gpu(host), m=16, dt=0.3, tau_step=0.3,
+                                        real_of_col=real)
+    Gb, _ = api.imag_two_point(T, 4, 2.5, taus, _gpu(host), m=16, tau_step=0.3, real_of_col=real)
+    for c in range(4):
+        Tc = api.Terms(N, Js[real[c]])
+        F1, Fi1, _ = api.otoc_unregularized(Tc, 2, 5, 2.5, times, _gpu(host[c]), m=16, dt=0.3, tau_step=0.3)
+        G1, _ = api.imag_two_point(Tc, 4, 2.5, taus, _gpu(host[c]), m=16, tau_step=0.3)
+        assert np.abs(Fb[:, c] - F1[:, 0]).max() <= 1e-12
+        assert np.abs(Fib[:, c] - Fi1[:, 0]).max() <= 1e-12
+        assert np.abs(Gb[:, c] - G1[:, 0]).max() <= 1e-12
+
+
 def test_otoc_cfg2_n32():
     """N=32, beta J = 10, Lanczos m=30, dt=0.05 on the GPU; the checker uses
     dt=0.5 on its sparse H (both converged to ~1e-12)."""
