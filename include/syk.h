@@ -210,6 +210,24 @@ syk_status syk_imag_two_point(syk_terms t, syk_dtype dtype, int i, double beta, 
 syk_status syk_spectrum_bounds(syk_terms t, syk_dtype dtype, int m, const void* psi0, double* e_min,
                                double* e_max, hipStream_t stream);
 
+/*
+ * Low-lying spectrum by Lanczos (the eigenvalue use of the Krylov method of
+ * the SI, section "Krylov subspace methods"; the paper's validity criterion
+ * counts the eigenstates within 1/beta of the ground state): m Lanczos steps
+ * with two passes of classical Gram-Schmidt against the whole basis, started
+ * from psi0 (device, one column, realisation 0).  evals (host, k): the k
+ * lowest Ritz values of the m x m tridiagonal projection, ascending; resid
+ * (host, k, may be NULL): their residual norms ||H y - theta y|| = beta_m
+ * |s_m| (each Ritz value lies within its residual of an eigenvalue);
+ * *n_found: how many were written (fewer than k if the Krylov space became
+ * invariant, in which case the residuals are 0).  A starting vector reaches
+ * one copy of each distinct level in exact arithmetic; in floating point
+ * copies of degenerate levels can appear late.  Holds m state vectors of
+ * workspace (2 <= m <= 1024, 1 <= k <= m).
+ */
+syk_status syk_lowest_eigenvalues(syk_terms t, syk_dtype dtype, int m, int k, const void* psi0, double* evals,
+                                  double* resid, int* n_found, hipStream_t stream);
+
 /* Chebyshev options.  Every propagator of the OTOC becomes a fixed polynomial
  * of this degree (2..256) in H~ = (H - e_center) / e_halfwidth: real time in
  * steps of dt (t_star must be a multiple of dt), each imaginary-time leg in

@@ -88,3 +88,42 @@ class DenseExp:
 
     def matrix(self, z: complex) -> np.ndarray:
         return (self.evecs * np.exp(z * self.evals)) @ self.evecs.conj().T
+
+
+def lanczos_ritz(matvec, psi: np.ndarray, m: int, breakdown_tol: float = 1e-13):
+    """Ritz values of H from an m-step Lanczos run started at psi (the same
+    projection as krylov_step: orthonormal basis by classical Gram-Schmidt
+    done twice, T tridiagonal).  Returns (theta ascending, residual norms
+    beta_k |s_{k,i}|), where s_i is the i-th eigenvector of T and beta_k the
+    coefficient that would start the next basis vector (0 when the space is
+    invariant: then theta are exact eigenvalues of H, one per distinct
+    eigenvalue that psi touches)."""
+    nrm = float(np.linalg.norm(psi))
+    V = np.zeros((m, psi.size), dtype=np.complex128)
+    V[0] = psi / nrm
+    alpha, beta = [], []
+    beta_last = 0.0
+    k = m
+    for j in range(m):
+        w = matvec(V[j]).astype(np.complex128)
+        Vj = V[: j + 1]
+        c1 = Vj.conj() @ w
+        w = w - Vj.T @ c1
+        c2 = Vj.conj() @ w
+        w = w - Vj.T @ c2
+        alpha.append(float((c1[j] + c2[j]).real))
+        b = float(np.linalg.norm(w))
+        scale = max(abs(a) for a in alpha) + (beta[-1] if beta else 0.0)
+        if j == m - 1:
+            beta_last = b
+            break
+        if b <= breakdown_tol * max(scale, 1e-300):
+            k = j + 1
+            break
+        beta.append(b)
+        V[j + 1] = w / b
+    a = np.array(alpha[:k])
+    if k == 1:
+        return a.copy(), np.zeros(1)
+    theta, S = scipy.linalg.eigh_tridiagonal(a, np.array(beta[: k - 1]))
+    return theta, beta_last * np.abs(S[-1, :])

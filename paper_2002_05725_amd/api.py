@@ -249,6 +249,22 @@ def spectrum_bounds(terms: Terms, psi0: torch.Tensor, m: int = 40):
     return lo.value, hi.value
 
 
+def lowest_eigenvalues(terms: Terms, psi0: torch.Tensor, k: int = 20, m: int = 200):
+    """(Ritz values, residual norms): the k lowest of m Lanczos steps from psi0
+    (numpy arrays of length <= k); see syk_lowest_eigenvalues."""
+    _check_state(psi0, terms.dim, "psi0")
+    if psi0.dim() != 1:
+        raise ValueError("eigenvalues take one state")
+    ev = np.empty(k)
+    res = np.empty(k)
+    n = ctypes.c_int()
+    check(lib().syk_lowest_eigenvalues(terms.handle, _dtype_code(psi0), int(m), int(k),
+                                       ctypes.c_void_p(psi0.data_ptr()), ev.ctypes.data_as(ctypes.c_void_p),
+                                       res.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n), _stream()),
+          "syk_lowest_eigenvalues")
+    return ev[:n.value].copy(), res[:n.value].copy()
+
+
 def cheb_opts(degree: int = 32, dt: float = 0.1, tau_steps: int = 1, checkpoint_every: int = 10,
               e_center: float = 0.0, e_halfwidth: float = 1.0) -> ChebOpts:
     return ChebOpts(int(degree), float(dt), int(tau_steps), int(checkpoint_every), float(e_center),

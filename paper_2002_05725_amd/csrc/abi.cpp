@@ -418,6 +418,21 @@ syk_status syk_spectrum_bounds(syk_terms t, syk_dtype dtype, int m, const void* 
     });
 }
 
+syk_status syk_lowest_eigenvalues(syk_terms t, syk_dtype dtype, int m, int k, const void* psi0, double* evals,
+                                  double* resid, int* n_found, hipStream_t stream)
+{
+    return guard([&] {
+        check_handle(t);
+        check_dtype(dtype);
+        require(m >= 2 && m <= 1024, "m must be in [2, 1024]");
+        require(k >= 1 && k <= m, "k must be in [1, m]");
+        check_ptr(psi0, "psi0");
+        require(evals != nullptr && n_found != nullptr, "outputs are NULL");
+        BlockCtx c(*t, dtype, 1, nullptr, stream);
+        *n_found = lowest_eigenvalues(c, psi0, m, k, evals, resid);
+    });
+}
+
 static ChebSettings check_cheb(syk_terms t, int i, int j, double beta, double t_star, const syk_cheb_opts* o)
 {
     check_handle(t);

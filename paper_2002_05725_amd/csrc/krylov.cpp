@@ -6,6 +6,8 @@
 // are FP64 on the host.
 #include "krylov.hpp"
 
+#include <algorithm>
+
 #include <cmath>
 
 namespace syk {
@@ -175,6 +177,26 @@ void lanczos_extremes(BlockCtx& c, const void* psi, int m, double* emin, double*
         *emin = std::min(*emin, e);
         *emax = std::max(*emax, e);
     }
+}
+
+int lowest_eigenvalues(BlockCtx& c, const void* psi, int m, int k, double* ev_out, double* res_out)
+{
+    require(c.nvec == 1, "eigenvalues: one column");
+    LanczosBasis L = lanczos_build(c, psi, m);
+    std::vector<double> ev, S;
+    ritz_values(L, 0, 1, ev, S);
+    const int kd = L.kdim[0];
+    std::vector<int> ord(kd);
+    for (int i = 0; i < kd; ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return ev[a] < ev[b]; });
+    // beta of the step that would extend the basis; 0 when the space is invariant
+    const double bl = (kd == m) ? L.beta[(size_t)(m - 1)] : 0.0;
+    const int n = std::min(k, kd);
+    for (int i = 0; i < n; ++i) {
+        ev_out[i] = ev[ord[i]];
+        if (res_out) res_out[i] = bl * std::fabs(S[(size_t)(kd - 1) * kd + ord[i]]);
+    }
+    return n;
 }
 
 void krylov_propagate(BlockCtx& c, void* psi, std::complex<double> z, double total, double step, int m,

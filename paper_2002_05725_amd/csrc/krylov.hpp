@@ -48,6 +48,11 @@ void ritz_values(const LanczosBasis& L, int col, int nvec, std::vector<double>& 
 // Smallest and largest Ritz values of m Lanczos steps from psi (one column).
 void lanczos_extremes(BlockCtx& c, const void* psi, int m, double* emin, double* emax);
 
+// The k lowest Ritz values of m Lanczos steps from psi (one column), ascending,
+// and their residual norms beta_m |s_m,i| (res_out may be NULL).  Returns how
+// many were written (fewer than k when the Krylov space became invariant).
+int lowest_eigenvalues(BlockCtx& c, const void* psi, int m, int k, double* ev_out, double* res_out);
+
 // psi <- exp(z H) psi per column with one Lanczos step of m vectors.
 void krylov_step(BlockCtx& c, void* psi, std::complex<double> z, int m, KrylovStats& st);
 

@@ -239,6 +239,53 @@ def test_unregularized_and_imag_blocks_match_columns():
         assert np.abs(Gb[:, c] - G1[:, 0]).max() <= 1e-12
 
 
+def test_lowest_eigenvalues_cover_dense_spectrum_n12():
+    """m = dim Lanczos on the GPU: every converged Ritz value is an eigenvalue
+    of the dense H and every distinct eigenvalue appears."""
+    N = 12
+    J = inputs.couplings(N, 0)
+    T = api.Terms(N, J)
+    ev = np.linalg.eigvalsh(jw.dense_H(N, J))
+    distinct = ev[np.concatenate(([True], np.diff(ev) > 1e-9))]
+    theta, res = api.lowest_eigenvalues(T, _gpu(inputs.typical_state(N, 1)), k=64, m=64)
+    good = theta[res < 1e-10]
+    assert np.abs(good[:, None] - ev[None, :]).min(axis=1).max() < 1e-11
+    assert np.abs(distinct[:, None] - good[None, :]).min(axis=1).max() < 1e-11
+
+
+def test_lowest_eigenvalues_n20_vs_dense_and_checker():
+    """N=20 (dim 1024), m = 120: the GPU Ritz values equal the checker's
+    Lanczos on the same state, and the converged low ones are eigenvalues."""
+    N = 20
+    J = inputs.couplings(N, 0)
+    psi = inputs.typical_state(N, 1)
+    T = api.Terms(N, J)
+    theta, res = api.lowest_eigenvalues(T, _gpu(psi), k=12, m=120)
+    H = jw.dense_H(N, J)
+    th_ref, res_ref = krylov.lanczos_ritz(lambda v: H @ v, psi, 120)
+    conv = res_ref[:12] < 1e-9
+    assert conv[:4].all()
+    assert np.abs(theta[conv] - th_ref[:12][conv]).max() < 1e-10
+    ev = np.linalg.eigvalsh(H)
+    assert np.abs(theta[conv][:, None] - ev[None, :]).min(axis=1).max() < 1e-10
+    assert np.all(np.abs(theta[:, None] - ev[None, :]).min(axis=1) <= res + 1e-12)
+
+
+def test_ground_state_energy_n28_vs_checker():
+    """N=28 (dim 16384): the lowest Ritz values and their residual norms
+    against the checker's Lanczos on its sparse H (same state, same m); the
+    same FP64 projection on both sides, whether or not it has converged."""
+    N = 28
+    J = inputs.couplings(N, 0)
+    psi = inputs.typical_state(N, 1)
+    T = api.Terms(N, J)
+    theta, res = api.lowest_eigenvalues(T, _gpu(psi), k=4, m=150)
+    sp = native.SparseH(N, J)
+    th_ref, res_ref = krylov.lanczos_ritz(sp, psi, 150)
+    assert np.abs(theta - th_ref[:4]).max() <= 1e-10 * abs(th_ref[0])
+    assert np.abs(res - res_ref[:4]).max() <= 1e-6 * max(res_ref[:4].max(), 1e-12) + 1e-12
+
+
 def test_otoc_cfg2_n32():
     """N=32, beta J = 10, Lanczos m=30, dt=0.05 on the GPU; the checker uses
     dt=0.5 on its sparse H (both converged to ~1e-12)."""

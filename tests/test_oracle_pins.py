@@ -403,3 +403,35 @@ def test_unreg_otoc_and_imag_two_point_identities():
     Gb = correlators.imag_two_point_trace(E, chis, 1, beta, beta - taus)
     assert np.abs(Gt - Gb).max() < 1e-13
     assert abs(Gt[0] - 0.5) < 1e-14
+
+
+# ------------------------------------------------------- Lanczos eigenvalues
+@pytest.mark.parametrize("N", [8, 10, 12])
+def test_lanczos_ritz_values_cover_the_spectrum(N):
+    """Run to the full dimension from a typical state, every Ritz value with a
+    small residual is an eigenvalue of the dense H (library eigvalsh), and
+    every distinct eigenvalue appears.  (In floating point the copies of a
+    degenerate level can reappear after rounding seeds the partner direction,
+    so multiplicities are not asserted.)"""
+    H = jw.dense_H(N, inputs.couplings(N, 4))
+    ev = np.linalg.eigvalsh(H)
+    distinct = ev[np.concatenate(([True], np.diff(ev) > 1e-9))]
+    theta, res = krylov.lanczos_ritz(lambda v: H @ v, inputs.typical_state(N, 2), H.shape[0])
+    good = theta[res < 1e-10]
+    assert np.abs(good[:, None] - ev[None, :]).min(axis=1).max() < 1e-11
+    assert np.abs(distinct[:, None] - good[None, :]).min(axis=1).max() < 1e-11
+
+
+def test_lanczos_ritz_residual_bound():
+    """With fewer steps than levels: each Ritz value lies within its residual
+    norm of an eigenvalue (Hermitian residual bound), the lowest Ritz value
+    is not below the lowest eigenvalue, and the ground state converges first."""
+    N = 14
+    H = jw.dense_H(N, inputs.couplings(N, 4))
+    ev = np.linalg.eigvalsh(H)
+    theta, res = krylov.lanczos_ritz(lambda v: H @ v, inputs.typical_state(N, 2), 60)
+    assert np.all(np.diff(theta) >= 0)
+    gap = np.abs(theta[:, None] - ev[None, :]).min(axis=1)
+    assert np.all(gap <= res + 1e-12)
+    assert theta[0] >= ev[0] - 1e-12
+    assert abs(theta[0] - ev[0]) < 1e-10
