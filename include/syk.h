@@ -228,6 +228,42 @@ syk_status syk_spectrum_bounds(syk_terms t, syk_dtype dtype, int m, const void* 
 syk_status syk_lowest_eigenvalues(syk_terms t, syk_dtype dtype, int m, int k, const void* psi0, double* evals,
                                   double* resid, int* n_found, hipStream_t stream);
 
+/*
+ * Fermion-parity sectors.  H conserves the parity of the qubit string (each
+ * term flips an even number of qubits; SI, section "Jordan-Wigner
+ * transformation"), and the paper evolves one sector.  A sector-s state
+ * (s = 0 or 1, N >= 6) holds the 2^(N/2 - 1) rows r with popcount(r) = s mod 2:
+ * entry u stands for the full row r = u + 2^(M-1) (parity(u) ^ s), M = N/2,
+ * i.e. the top qubit is implied.  Blocks, dtypes, memory, streams and errors
+ * as above.  The calls below are the full-space calls restricted to a sector:
+ * apply_H, krylov_expmv, two_point, otoc, otoc_unregularized and
+ * imag_two_point keep the sector of psi (Majoranas inside the estimators move
+ * between sectors as they must); syk_apply_majorana_sector maps a sector_in
+ * state to the other sector.  The handle builds each sector's tables on first
+ * use (QUAD masks on the top qubit become two three-qubit masks, PAIR masks a
+ * main and a parity part).
+ */
+syk_status syk_apply_H_sector(syk_terms t, syk_dtype dtype, int sector, int nvec, const int32_t* real_of_col,
+                              const void* psi, void* out, hipStream_t stream);
+syk_status syk_apply_majorana_sector(syk_terms t, syk_dtype dtype, int a, int sector_in, int nvec, const void* psi,
+                                     void* out, hipStream_t stream);
+syk_status syk_krylov_expmv_sector(syk_terms t, syk_dtype dtype, int sector, int nvec, const int32_t* real_of_col,
+                                   double z_re, double z_im, double total, const syk_krylov_opts* opts,
+                                   void* psi_inout, double* err_est, hipStream_t stream);
+syk_status syk_two_point_sector(syk_terms t, syk_dtype dtype, int sector, int i, double beta, const double* times,
+                                int nt, int nvec, const int32_t* real_of_col, const void* psi0,
+                                const syk_krylov_opts* opts, double* G, double* Z, hipStream_t stream);
+syk_status syk_otoc_sector(syk_terms t, syk_dtype dtype, int sector, int i, int j, double beta, const double* times,
+                           int nt, int nvec, const int32_t* real_of_col, const void* psi0, const syk_krylov_opts* opts,
+                           double* F, double* F_im, double* Z, hipStream_t stream);
+syk_status syk_otoc_unregularized_sector(syk_terms t, syk_dtype dtype, int sector, int i, int j, double beta,
+                                         const double* times, int nt, int nvec, const int32_t* real_of_col,
+                                         const void* psi0, const syk_krylov_opts* opts, double* F, double* F_im,
+                                         double* Z, hipStream_t stream);
+syk_status syk_imag_two_point_sector(syk_terms t, syk_dtype dtype, int sector, int i, double beta, const double* taus,
+                                     int ntau, int nvec, const int32_t* real_of_col, const void* psi0,
+                                     const syk_krylov_opts* opts, double* G, double* Z, hipStream_t stream);
+
 /* Chebyshev options.  Every propagator of the OTOC becomes a fixed polynomial
  * of this degree (2..256) in H~ = (H - e_center) / e_halfwidth: real time in
  * steps of dt (t_star must be a multiple of dt), each imaginary-time leg in

@@ -93,3 +93,17 @@ def parity_operator(N: int) -> np.ndarray:
     D = 1 << (N // 2)
     s = np.arange(D, dtype=np.uint64)
     return np.where(np.bitwise_count(s) % 2 == 0, 1.0, -1.0)
+
+
+def sector_rows(N: int, s: int) -> np.ndarray:
+    """Full-space rows of the fermion-parity sector s (popcount(r) = s mod 2),
+    in the order of the sector index u: r = u + 2^(M-1) (parity(u) ^ s), M = N/2.
+    (H conserves the parity of the qubit string; each Majorana flips it.)"""
+    M = N // 2
+    u = np.arange(1 << (M - 1), dtype=np.int64)
+    par = np.zeros_like(u)
+    v = u.copy()
+    while v.any():
+        par ^= v & 1
+        v >>= 1
+    return u + ((par ^ s) << (M - 1))

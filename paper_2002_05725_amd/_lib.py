@@ -56,6 +56,17 @@ _SIGS = {
     "syk_dot": (_i, [_i, _i64, _i, _vp, _vp, _vp, _vp]),
     "syk_krylov_expmv": (_i, [_vp, _i, _i, _vp, _d, _d, _d, ctypes.POINTER(KrylovOpts), _vp, _vp, _vp]),
     "syk_two_point": (_i, [_vp, _i, _i, _d, _vp, _i, _i, _vp, _vp, ctypes.POINTER(KrylovOpts), _vp, _vp, _vp]),
+    "syk_apply_H_sector": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp]),
+    "syk_apply_majorana_sector": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp]),
+    "syk_krylov_expmv_sector": (_i, [_vp, _i, _i, _i, _vp, _d, _d, _d, ctypes.POINTER(KrylovOpts), _vp, _vp, _vp]),
+    "syk_two_point_sector": (_i, [_vp, _i, _i, _i, _d, _vp, _i, _i, _vp, _vp, ctypes.POINTER(KrylovOpts), _vp, _vp,
+                                  _vp]),
+    "syk_otoc_sector": (_i, [_vp, _i, _i, _i, _i, _d, _vp, _i, _i, _vp, _vp, ctypes.POINTER(KrylovOpts), _vp, _vp,
+                             _vp, _vp]),
+    "syk_otoc_unregularized_sector": (_i, [_vp, _i, _i, _i, _i, _d, _vp, _i, _i, _vp, _vp, ctypes.POINTER(KrylovOpts),
+                                           _vp, _vp, _vp, _vp]),
+    "syk_imag_two_point_sector": (_i, [_vp, _i, _i, _i, _d, _vp, _i, _i, _vp, _vp, ctypes.POINTER(KrylovOpts), _vp,
+                                       _vp, _vp]),
     "syk_lowest_eigenvalues": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_int), _vp]),
     "syk_otoc_unregularized": (_i, [_vp, _i, _i, _i, _d, _vp, _i, _i, _vp, _vp, ctypes.POINTER(KrylovOpts), _vp,
                                     _vp, _vp, _vp]),

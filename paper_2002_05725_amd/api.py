@@ -4,6 +4,9 @@ of the computation runs in the HIP library.
 
 States are complex torch tensors on the GPU, shape [dim] (one vector) or
 [nvec, dim] (a block of nvec states, each row one state, as the library expects).
+Calls that take `sector` (0 or 1) work on fermion-parity-sector states of
+dim // 2 entries instead (see syk.h: entry u is the full row u + 2^(M-1)
+(parity(u) ^ sector)).
 """
 from __future__ import annotations
 
@@ -39,6 +42,14 @@ def _check_state(t: torch.Tensor, dim: int, name: str):
         raise ValueError(f"{name} must be contiguous")
     if t.dim() not in (1, 2) or t.shape[-1] != dim:
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected [{dim}] or [nvec, {dim}]")
+
+
+def _sdim(terms, sector):
+    if sector is None:
+        return terms.dim
+    if sector not in (0, 1):
+        raise ValueError("sector must be 0, 1 or None")
+    return terms.dim // 2
 
 
 def _stream() -> ctypes.c_void_p:
@@ -120,25 +131,36 @@ def build_terms(N: int, J) -> Terms:
     return Terms(N, J)
 
 
-def apply_H(terms: Terms, psi: torch.Tensor, out: torch.Tensor | None = None, real_of_col=None) -> torch.Tensor:
-    _check_state(psi, terms.dim, "psi")
+def apply_H(terms: Terms, psi: torch.Tensor, out: torch.Tensor | None = None, real_of_col=None,
+            sector: int | None = None) -> torch.Tensor:
+    d = _sdim(terms, sector)
+    _check_state(psi, d, "psi")
     nvec = _nvec(psi)
     if out is None:
         out = torch.empty_like(psi)
-    _check_state(out, terms.dim, "out")
+    _check_state(out, d, "out")
     ra, rp = _real_arr(real_of_col, nvec)
-    check(lib().syk_apply_H(terms.handle, _dtype_code(psi), nvec, rp, ctypes.c_void_p(psi.data_ptr()),
-                            ctypes.c_void_p(out.data_ptr()), _stream()), "syk_apply_H")
+    args = (ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream())
+    if sector is None:
+        check(lib().syk_apply_H(terms.handle, _dtype_code(psi), nvec, rp, *args), "syk_apply_H")
+    else:
+        check(lib().syk_apply_H_sector(terms.handle, _dtype_code(psi), int(sector), nvec, rp, *args),
+              "syk_apply_H_sector")
     return out
 
 
-def apply_majorana(terms: Terms, a: int, psi: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-    _check_state(psi, terms.dim, "psi")
+def apply_majorana(terms: Terms, a: int, psi: torch.Tensor, out: torch.Tensor | None = None,
+                   sector: int | None = None) -> torch.Tensor:
+    """chi_a psi; with `sector` psi is a state of that sector and the result one of the other."""
+    _check_state(psi, _sdim(terms, sector), "psi")
     if out is None:
         out = torch.empty_like(psi)
-    check(lib().syk_apply_majorana(terms.handle, _dtype_code(psi), int(a), _nvec(psi),
-                                   ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream()),
-          "syk_apply_majorana")
+    args = (_nvec(psi), ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream())
+    if sector is None:
+        check(lib().syk_apply_majorana(terms.handle, _dtype_code(psi), int(a), *args), "syk_apply_majorana")
+    else:
+        check(lib().syk_apply_majorana_sector(terms.handle, _dtype_code(psi), int(a), int(sector), *args),
+              "syk_apply_majorana_sector")
     return out
 
 
@@ -154,40 +176,54 @@ def dot(a: torch.Tensor, b: torch.Tensor) -> np.ndarray:
 
 
 def krylov_expmv(terms: Terms, psi: torch.Tensor, z: complex, total: float, m: int = 20, dt: float = 0.1,
-                 tau_step: float = 0.1, tol: float = 0.0, real_of_col=None) -> np.ndarray:
+                 tau_step: float = 0.1, tol: float = 0.0, real_of_col=None, sector: int | None = None) -> np.ndarray:
     """psi <- exp(total * z * H) psi in place; returns the per-column error estimate."""
-    _check_state(psi, terms.dim, "psi")
+    _check_state(psi, _sdim(terms, sector), "psi")
     nvec = _nvec(psi)
     ra, rp = _real_arr(real_of_col, nvec)
     err = np.zeros(nvec)
     o = _opts(m, dt, tau_step, tol)
-    check(lib().syk_krylov_expmv(terms.handle, _dtype_code(psi), nvec, rp, float(np.real(z)), float(np.imag(z)),
-                                 float(total), ctypes.byref(o), ctypes.c_void_p(psi.data_ptr()),
-                                 err.ctypes.data_as(ctypes.c_void_p), _stream()), "syk_krylov_expmv")
+    tail = (float(np.real(z)), float(np.imag(z)), float(total), ctypes.byref(o), ctypes.c_void_p(psi.data_ptr()),
+            err.ctypes.data_as(ctypes.c_void_p), _stream())
+    if sector is None:
+        check(lib().syk_krylov_expmv(terms.handle, _dtype_code(psi), nvec, rp, *tail), "syk_krylov_expmv")
+    else:
+        check(lib().syk_krylov_expmv_sector(terms.handle, _dtype_code(psi), int(sector), nvec, rp, *tail),
+              "syk_krylov_expmv_sector")
     return err
 
 
+def _call(name: str, terms: Terms, psi: torch.Tensor, sector, *rest):
+    """lib().name(handle, dtype, *rest), or name_sector with the sector after the dtype."""
+    if sector is None:
+        check(getattr(lib(), name)(terms.handle, _dtype_code(psi), *rest), name)
+    else:
+        check(getattr(lib(), name + "_sector")(terms.handle, _dtype_code(psi), int(sector), *rest), name + "_sector")
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
 def two_point(terms: Terms, i: int, beta: float, times, psi0: torch.Tensor, m: int = 20, dt: float = 0.1,
-              tau_step: float = 0.1, real_of_col=None):
+              tau_step: float = 0.1, real_of_col=None, sector: int | None = None):
     """G(t) (complex [nt, nvec]) and Z ([nvec]); see syk_two_point."""
-    _check_state(psi0, terms.dim, "psi0")
+    _check_state(psi0, _sdim(terms, sector), "psi0")
     nvec = _nvec(psi0)
     t = np.ascontiguousarray(times, dtype=np.float64)
     G = np.empty((t.size, nvec, 2))
     Z = np.empty(nvec)
     ra, rp = _real_arr(real_of_col, nvec)
     o = _opts(m, dt, tau_step, 0.0)
-    check(lib().syk_two_point(terms.handle, _dtype_code(psi0), int(i), float(beta),
-                              t.ctypes.data_as(ctypes.c_void_p), t.size, nvec, rp, ctypes.c_void_p(psi0.data_ptr()),
-                              ctypes.byref(o), G.ctypes.data_as(ctypes.c_void_p), Z.ctypes.data_as(ctypes.c_void_p),
-                              _stream()), "syk_two_point")
+    _call("syk_two_point", terms, psi0, sector, int(i), float(beta), _ptr(t), t.size, nvec, rp,
+          ctypes.c_void_p(psi0.data_ptr()), ctypes.byref(o), _ptr(G), _ptr(Z), _stream())
     return G[..., 0] + 1j * G[..., 1], Z
 
 
 def otoc(terms: Terms, i: int, j: int, beta: float, times, psi0: torch.Tensor, m: int = 20, dt: float = 0.1,
-         tau_step: float = 0.1, tol: float = 0.0, real_of_col=None):
+         tau_step: float = 0.1, tol: float = 0.0, real_of_col=None, sector: int | None = None):
     """F(t) ([nt, nvec]), Im part ([nt, nvec]) and Z ([nvec]); see syk_otoc."""
-    _check_state(psi0, terms.dim, "psi0")
+    _check_state(psi0, _sdim(terms, sector), "psi0")
     nvec = _nvec(psi0)
     t = np.ascontiguousarray(times, dtype=np.float64)
     F = np.empty((t.size, nvec))
@@ -195,18 +231,17 @@ def otoc(terms: Terms, i: int, j: int, beta: float, times, psi0: torch.Tensor, m
     Z = np.empty(nvec)
     ra, rp = _real_arr(real_of_col, nvec)
     o = _opts(m, dt, tau_step, tol)
-    check(lib().syk_otoc(terms.handle, _dtype_code(psi0), int(i), int(j), float(beta),
-                         t.ctypes.data_as(ctypes.c_void_p), t.size, nvec, rp, ctypes.c_void_p(psi0.data_ptr()),
-                         ctypes.byref(o), F.ctypes.data_as(ctypes.c_void_p), Fi.ctypes.data_as(ctypes.c_void_p),
-                         Z.ctypes.data_as(ctypes.c_void_p), _stream()), "syk_otoc")
+    _call("syk_otoc", terms, psi0, sector, int(i), int(j), float(beta), _ptr(t), t.size, nvec, rp,
+          ctypes.c_void_p(psi0.data_ptr()), ctypes.byref(o), _ptr(F), _ptr(Fi), _ptr(Z), _stream())
     return F, Fi, Z
 
 
 def otoc_unregularized(terms: Terms, i: int, j: int, beta: float, times, psi0: torch.Tensor, m: int = 20,
-                       dt: float = 0.1, tau_step: float = 0.1, tol: float = 0.0, real_of_col=None):
+                       dt: float = 0.1, tau_step: float = 0.1, tol: float = 0.0, real_of_col=None,
+                       sector: int | None = None):
     """Unregularized OTOC: Re F_u ([nt, nvec]), Im F_u ([nt, nvec]) and Z ([nvec]);
     see syk_otoc_unregularized."""
-    _check_state(psi0, terms.dim, "psi0")
+    _check_state(psi0, _sdim(terms, sector), "psi0")
     nvec = _nvec(psi0)
     t = np.ascontiguousarray(times, dtype=np.float64)
     F = np.empty((t.size, nvec))
@@ -214,29 +249,23 @@ def otoc_unregularized(terms: Terms, i: int, j: int, beta: float, times, psi0: t
     Z = np.empty(nvec)
     ra, rp = _real_arr(real_of_col, nvec)
     o = _opts(m, dt, tau_step, tol)
-    check(lib().syk_otoc_unregularized(terms.handle, _dtype_code(psi0), int(i), int(j), float(beta),
-                                       t.ctypes.data_as(ctypes.c_void_p), t.size, nvec, rp,
-                                       ctypes.c_void_p(psi0.data_ptr()), ctypes.byref(o),
-                                       F.ctypes.data_as(ctypes.c_void_p), Fi.ctypes.data_as(ctypes.c_void_p),
-                                       Z.ctypes.data_as(ctypes.c_void_p), _stream()), "syk_otoc_unregularized")
+    _call("syk_otoc_unregularized", terms, psi0, sector, int(i), int(j), float(beta), _ptr(t), t.size, nvec, rp,
+          ctypes.c_void_p(psi0.data_ptr()), ctypes.byref(o), _ptr(F), _ptr(Fi), _ptr(Z), _stream())
     return F, Fi, Z
 
 
 def imag_two_point(terms: Terms, i: int, beta: float, taus, psi0: torch.Tensor, m: int = 20, tau_step: float = 0.1,
-                   real_of_col=None):
+                   real_of_col=None, sector: int | None = None):
     """G(tau) ([ntau, nvec], real) and Z ([nvec]); see syk_imag_two_point."""
-    _check_state(psi0, terms.dim, "psi0")
+    _check_state(psi0, _sdim(terms, sector), "psi0")
     nvec = _nvec(psi0)
     tau = np.ascontiguousarray(taus, dtype=np.float64)
     G = np.empty((tau.size, nvec))
     Z = np.empty(nvec)
     ra, rp = _real_arr(real_of_col, nvec)
     o = _opts(m, 0.1, tau_step, 0.0)
-    check(lib().syk_imag_two_point(terms.handle, _dtype_code(psi0), int(i), float(beta),
-                                   tau.ctypes.data_as(ctypes.c_void_p), tau.size, nvec, rp,
-                                   ctypes.c_void_p(psi0.data_ptr()), ctypes.byref(o),
-                                   G.ctypes.data_as(ctypes.c_void_p), Z.ctypes.data_as(ctypes.c_void_p), _stream()),
-          "syk_imag_two_point")
+    _call("syk_imag_two_point", terms, psi0, sector, int(i), float(beta), _ptr(tau), tau.size, nvec, rp,
+          ctypes.c_void_p(psi0.data_ptr()), ctypes.byref(o), _ptr(G), _ptr(Z), _stream())
     return G, Z
 
 

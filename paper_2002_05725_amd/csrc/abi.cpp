@@ -47,6 +47,13 @@ void check_block(syk_terms t, int nvec, const int32_t* real)
             require(real[c] >= 0 && real[c] < t->host.n_real, "real_of_col entry out of range");
 }
 
+void check_sector(syk_terms t, int sector)
+{
+    if (!t) throw Error(SYK_EINVAL, "handle is NULL");
+    require(sector == 0 || sector == 1, "sector must be 0 or 1");
+    require(t->H.N >= 6, "parity sectors need N >= 6");
+}
+
 void check_ptr(const void* p, const char* what)
 {
     require(p != nullptr, std::string(what) + " is NULL");
@@ -138,11 +145,62 @@ int HamiltonianDev::n_far_for(int tile_bits) const
 
 }  // namespace syk
 
+namespace syk {
+
+// Device copies of a table set and the kernels' view of them.
+void make_device(const TermTables& T, DeviceTerms& d, HamiltonianDev& H)
+{
+    upload(d.masks, T.masks);
+    upload(d.tab4_d, T.tab4);
+    upload(d.tab4_f, to_c64(T.tab4));
+    upload(d.qinfo, T.qinfo);
+    upload(d.phi2_d, T.phi2);
+    upload(d.phi2_f, to_c64(T.phi2));
+    upload(d.w2_d, T.w2);
+    upload(d.w2_f, to_f32(T.w2));
+    upload(d.dz, T.dz);
+    upload(d.dw_d, T.dw);
+    upload(d.dw_f, to_f32(T.dw));
+    H.N = T.N;
+    H.M = T.M;
+    H.n_real = T.n_real;
+    H.n_diag = T.n_diag;
+    H.masks = d.masks.as<MaskRec>();
+    H.tab4_d = d.tab4_d.as<c128>();
+    H.tab4_f = d.tab4_f.as<c64>();
+    H.qinfo = d.qinfo.as<uint32_t>();
+    H.phi2_d = d.phi2_d.as<c128>();
+    H.phi2_f = d.phi2_f.as<c64>();
+    H.w2_d = d.w2_d.as<double>();
+    H.w2_f = d.w2_f.as<float>();
+    H.dz = d.dz.as<uint32_t>();
+    H.dw_d = d.dw_d.as<double>();
+    H.dw_f = d.dw_f.as<float>();
+    H.host_masks = &T.masks;
+    H.bin_off = &T.bin_off;
+}
+
+const HamiltonianDev& sector_ham(syk_terms_s& h, int s)
+{
+    require(s == 0 || s == 1, "sector must be 0 or 1");
+    auto& p = h.sectors[s];
+    if (!p) {
+        std::unique_ptr<syk_terms_s::Sector> n(new syk_terms_s::Sector());
+        build_sector_tables(h.host, s, n->host);
+        make_device(n->host, n->dev, n->H);
+        p = std::move(n);
+    }
+    return p->H;
+}
+
+}  // namespace syk
+
 extern "C" {
 
 const char* syk_last_error(void) { return g_last_error.c_str(); }
 
 int syk_version(void) { return 100; }
+
 
 syk_status syk_build_terms(int N, int n_real, const double* J, syk_terms* out)
 {
@@ -157,37 +215,7 @@ syk_status syk_build_terms(int N, int n_real, const double* J, syk_terms* out)
         std::unique_ptr<syk_terms_s> h(new syk_terms_s());
         SYK_HIP(hipGetDevice(&h->device));
         build_tables(N, n_real, J, h->host);
-        const TermTables& T = h->host;
-        DeviceTerms& d = h->dev;
-        upload(d.masks, T.masks);
-        upload(d.tab4_d, T.tab4);
-        upload(d.tab4_f, to_c64(T.tab4));
-        upload(d.qinfo, T.qinfo);
-        upload(d.phi2_d, T.phi2);
-        upload(d.phi2_f, to_c64(T.phi2));
-        upload(d.w2_d, T.w2);
-        upload(d.w2_f, to_f32(T.w2));
-        upload(d.dz, T.dz);
-        upload(d.dw_d, T.dw);
-        upload(d.dw_f, to_f32(T.dw));
-        HamiltonianDev& H = h->H;
-        H.N = N;
-        H.M = N / 2;
-        H.n_real = n_real;
-        H.n_diag = T.n_diag;
-        H.masks = d.masks.as<MaskRec>();
-        H.tab4_d = d.tab4_d.as<c128>();
-        H.tab4_f = d.tab4_f.as<c64>();
-        H.qinfo = d.qinfo.as<uint32_t>();
-        H.phi2_d = d.phi2_d.as<c128>();
-        H.phi2_f = d.phi2_f.as<c64>();
-        H.w2_d = d.w2_d.as<double>();
-        H.w2_f = d.w2_f.as<float>();
-        H.dz = d.dz.as<uint32_t>();
-        H.dw_d = d.dw_d.as<double>();
-        H.dw_f = d.dw_f.as<float>();
-        H.host_masks = &T.masks;
-        H.bin_off = &T.bin_off;
+        make_device(h->host, h->dev, h->H);
         *out = h.release();
     });
 }
@@ -209,19 +237,33 @@ syk_status syk_terms_info(syk_terms t, int* N, int* n_real, int64_t* dim, int64_
     });
 }
 
+static void apply_impl(syk_terms t, syk_dtype dtype, int sector, int nvec, const int32_t* real_of_col,
+                       const void* psi, void* out, hipStream_t stream)
+{
+    check_handle(t);
+    check_dtype(dtype);
+    check_block(t, nvec, real_of_col);
+    check_ptr(psi, "psi");
+    check_ptr(out, "out");
+    const HamiltonianDev& H = sector < 0 ? t->H : sector_ham(*t, sector);
+    const size_t bytes = ((size_t)1 << H.M) * nvec * elem_bytes(dtype);
+    check_no_overlap(psi, out, bytes);
+    ApplyPlan P = plan_for(*t, H.M, nvec, dtype);
+    launch_apply_h(H, dtype, nvec, real_of_col, psi, out, P, stream);
+}
+
 syk_status syk_apply_H(syk_terms t, syk_dtype dtype, int nvec, const int32_t* real_of_col, const void* psi,
                        void* out, hipStream_t stream)
 {
+    return guard([&] { apply_impl(t, dtype, -1, nvec, real_of_col, psi, out, stream); });
+}
+
+syk_status syk_apply_H_sector(syk_terms t, syk_dtype dtype, int sector, int nvec, const int32_t* real_of_col,
+                              const void* psi, void* out, hipStream_t stream)
+{
     return guard([&] {
-        check_handle(t);
-        check_dtype(dtype);
-        check_block(t, nvec, real_of_col);
-        check_ptr(psi, "psi");
-        check_ptr(out, "out");
-        const size_t bytes = ((size_t)1 << t->H.M) * nvec * elem_bytes(dtype);
-        check_no_overlap(psi, out, bytes);
-        ApplyPlan P = plan_for(*t, nvec, dtype);
-        launch_apply_h(t->H, dtype, nvec, real_of_col, psi, out, P, stream);
+        check_sector(t, sector);
+        apply_impl(t, dtype, sector, nvec, real_of_col, psi, out, stream);
     });
 }
 
@@ -266,19 +308,34 @@ syk_status syk_timing_reset(void)
     return guard([&] { timing_reset(); });
 }
 
+static void majorana_impl(syk_terms t, syk_dtype dtype, int a, int sector, int nvec, const void* psi, void* out,
+                          hipStream_t stream)
+{
+    check_handle(t);
+    check_dtype(dtype);
+    require(a >= 0 && a < t->H.N, "Majorana index out of range");
+    require(nvec >= 1, "nvec must be >= 1");
+    check_ptr(psi, "psi");
+    check_ptr(out, "out");
+    const int M = sector < 0 ? t->H.M : t->H.M - 1;
+    VecOps ops(*t, dtype, (int64_t)1 << M, nvec, stream);
+    check_no_overlap(psi, out, ops.vec_bytes());
+    if (sector < 0) ops.majorana(a, psi, out);
+    else ops.majorana_sector(a, M, sector, psi, out);
+}
+
 syk_status syk_apply_majorana(syk_terms t, syk_dtype dtype, int a, int nvec, const void* psi, void* out,
                               hipStream_t stream)
 {
+    return guard([&] { majorana_impl(t, dtype, a, -1, nvec, psi, out, stream); });
+}
+
+syk_status syk_apply_majorana_sector(syk_terms t, syk_dtype dtype, int a, int sector_in, int nvec, const void* psi,
+                                     void* out, hipStream_t stream)
+{
     return guard([&] {
-        check_handle(t);
-        check_dtype(dtype);
-        require(a >= 0 && a < t->H.N, "Majorana index out of range");
-        require(nvec >= 1, "nvec must be >= 1");
-        check_ptr(psi, "psi");
-        check_ptr(out, "out");
-        VecOps ops(*t, dtype, (int64_t)1 << t->H.M, nvec, stream);
-        check_no_overlap(psi, out, ops.vec_bytes());
-        ops.majorana(a, psi, out);
+        check_sector(t, sector_in);
+        majorana_impl(t, dtype, a, sector_in, nvec, psi, out, stream);
     });
 }
 
@@ -303,11 +360,11 @@ syk_status syk_dot(syk_dtype dtype, int64_t dim, int nvec, const void* a, const 
     });
 }
 
-syk_status syk_krylov_expmv(syk_terms t, syk_dtype dtype, int nvec, const int32_t* real_of_col, double z_re,
-                            double z_im, double total, const syk_krylov_opts* opts, void* psi_inout,
-                            double* err_est, hipStream_t stream)
+static void expmv_impl(syk_terms t, syk_dtype dtype, int sector, int nvec, const int32_t* real_of_col, double z_re,
+                       double z_im, double total, const syk_krylov_opts* opts, void* psi_inout, double* err_est,
+                       hipStream_t stream)
 {
-    return guard([&] {
+    {
         check_handle(t);
         check_dtype(dtype);
         check_block(t, nvec, real_of_col);
@@ -315,7 +372,7 @@ syk_status syk_krylov_expmv(syk_terms t, syk_dtype dtype, int nvec, const int32_
         check_ptr(psi_inout, "psi");
         require(std::isfinite(z_re) && std::isfinite(z_im) && std::isfinite(total) && total >= 0,
                 "z and total must be finite, total >= 0");
-        BlockCtx c(*t, dtype, nvec, real_of_col, stream);
+        BlockCtx c(*t, dtype, nvec, real_of_col, stream, sector);
         KrylovStats st;
         st.err.assign(nvec, 0.0);
         const double step = (z_re == 0.0) ? o.dt : o.tau_step;
@@ -326,14 +383,31 @@ syk_status syk_krylov_expmv(syk_terms t, syk_dtype dtype, int nvec, const int32_
         if (o.tol > 0)
             for (double e : st.err)
                 if (e > o.tol) throw Error(SYK_ENOTCONVERGED, "Krylov error estimate above tolerance");
+    }
+}
+
+syk_status syk_krylov_expmv(syk_terms t, syk_dtype dtype, int nvec, const int32_t* real_of_col, double z_re,
+                            double z_im, double total, const syk_krylov_opts* opts, void* psi_inout,
+                            double* err_est, hipStream_t stream)
+{
+    return guard([&] { expmv_impl(t, dtype, -1, nvec, real_of_col, z_re, z_im, total, opts, psi_inout, err_est, stream); });
+}
+
+syk_status syk_krylov_expmv_sector(syk_terms t, syk_dtype dtype, int sector, int nvec, const int32_t* real_of_col,
+                                   double z_re, double z_im, double total, const syk_krylov_opts* opts,
+                                   void* psi_inout, double* err_est, hipStream_t stream)
+{
+    return guard([&] {
+        check_sector(t, sector);
+        expmv_impl(t, dtype, sector, nvec, real_of_col, z_re, z_im, total, opts, psi_inout, err_est, stream);
     });
 }
 
-syk_status syk_two_point(syk_terms t, syk_dtype dtype, int i, double beta, const double* times, int nt, int nvec,
+static void two_point_impl(int sector, syk_terms t, syk_dtype dtype, int i, double beta, const double* times, int nt, int nvec,
                          const int32_t* real_of_col, const void* psi0, const syk_krylov_opts* opts, double* G,
                          double* Z, hipStream_t stream)
 {
-    return guard([&] {
+    {
         check_handle(t);
         check_dtype(dtype);
         check_block(t, nvec, real_of_col);
@@ -342,16 +416,16 @@ syk_status syk_two_point(syk_terms t, syk_dtype dtype, int i, double beta, const
         require(std::isfinite(beta) && beta >= 0, "beta must be finite and >= 0");
         check_ptr(psi0, "psi0");
         require(G != nullptr, "G is NULL");
-        BlockCtx c(*t, dtype, nvec, real_of_col, stream);
+        BlockCtx c(*t, dtype, nvec, real_of_col, stream, sector);
         two_point(c, i, beta, times, nt, psi0, o, G, Z);
-    });
+    }
 }
 
-syk_status syk_otoc(syk_terms t, syk_dtype dtype, int i, int j, double beta, const double* times, int nt, int nvec,
+static void otoc_impl(int sector, syk_terms t, syk_dtype dtype, int i, int j, double beta, const double* times, int nt, int nvec,
                     const int32_t* real_of_col, const void* psi0, const syk_krylov_opts* opts, double* F,
                     double* F_im, double* Z, hipStream_t stream)
 {
-    return guard([&] {
+    {
         check_handle(t);
         check_dtype(dtype);
         check_block(t, nvec, real_of_col);
@@ -361,8 +435,80 @@ syk_status syk_otoc(syk_terms t, syk_dtype dtype, int i, int j, double beta, con
         require(std::isfinite(beta) && beta >= 0, "beta must be finite and >= 0");
         check_ptr(psi0, "psi0");
         require(F != nullptr, "F is NULL");
-        BlockCtx c(*t, dtype, nvec, real_of_col, stream);
+        BlockCtx c(*t, dtype, nvec, real_of_col, stream, sector);
         otoc(c, i, j, beta, times, nt, psi0, o, F, F_im, Z);
+    }
+}
+
+static void otoc_unregularized_impl(int sector, syk_terms t, syk_dtype dtype, int i, int j, double beta, const double* times,
+                                  int nt, int nvec, const int32_t* real_of_col, const void* psi0,
+                                  const syk_krylov_opts* opts, double* F, double* F_im, double* Z,
+                                  hipStream_t stream)
+{
+    {
+        check_handle(t);
+        check_dtype(dtype);
+        check_block(t, nvec, real_of_col);
+        syk_krylov_opts o = check_opts(opts);
+        require(i >= 0 && i < t->H.N && j >= 0 && j < t->H.N, "Majorana index out of range");
+        require(i != j, "the OTOC needs i != j");
+        require(std::isfinite(beta) && beta >= 0, "beta must be finite and >= 0");
+        check_ptr(psi0, "psi0");
+        require(F != nullptr, "F is NULL");
+        BlockCtx c(*t, dtype, nvec, real_of_col, stream, sector);
+        otoc_unregularized(c, i, j, beta, times, nt, psi0, o, F, F_im, Z);
+    }
+}
+
+static void imag_two_point_impl(int sector, syk_terms t, syk_dtype dtype, int i, double beta, const double* taus, int ntau,
+                              int nvec, const int32_t* real_of_col, const void* psi0, const syk_krylov_opts* opts,
+                              double* G, double* Z, hipStream_t stream)
+{
+    {
+        check_handle(t);
+        check_dtype(dtype);
+        check_block(t, nvec, real_of_col);
+        syk_krylov_opts o = check_opts(opts);
+        require(i >= 0 && i < t->H.N, "Majorana index out of range");
+        require(std::isfinite(beta) && beta >= 0, "beta must be finite and >= 0");
+        check_ptr(psi0, "psi0");
+        require(G != nullptr, "G is NULL");
+        BlockCtx c(*t, dtype, nvec, real_of_col, stream, sector);
+        imag_two_point(c, i, beta, taus, ntau, psi0, o, G, Z);
+    }
+}
+
+syk_status syk_two_point(syk_terms t, syk_dtype dtype, int i, double beta, const double* times, int nt, int nvec,
+                         const int32_t* real_of_col, const void* psi0, const syk_krylov_opts* opts, double* G,
+                         double* Z, hipStream_t stream)
+{
+    return guard([&] { two_point_impl(-1, t, dtype, i, beta, times, nt, nvec, real_of_col, psi0, opts, G, Z, stream); });
+}
+
+syk_status syk_two_point_sector(syk_terms t, syk_dtype dtype, int sector, int i, double beta, const double* times,
+                                int nt, int nvec, const int32_t* real_of_col, const void* psi0,
+                                const syk_krylov_opts* opts, double* G, double* Z, hipStream_t stream)
+{
+    return guard([&] {
+        check_sector(t, sector);
+        two_point_impl(sector, t, dtype, i, beta, times, nt, nvec, real_of_col, psi0, opts, G, Z, stream);
+    });
+}
+
+syk_status syk_otoc(syk_terms t, syk_dtype dtype, int i, int j, double beta, const double* times, int nt, int nvec,
+                    const int32_t* real_of_col, const void* psi0, const syk_krylov_opts* opts, double* F,
+                    double* F_im, double* Z, hipStream_t stream)
+{
+    return guard([&] { otoc_impl(-1, t, dtype, i, j, beta, times, nt, nvec, real_of_col, psi0, opts, F, F_im, Z, stream); });
+}
+
+syk_status syk_otoc_sector(syk_terms t, syk_dtype dtype, int sector, int i, int j, double beta, const double* times,
+                           int nt, int nvec, const int32_t* real_of_col, const void* psi0, const syk_krylov_opts* opts,
+                           double* F, double* F_im, double* Z, hipStream_t stream)
+{
+    return guard([&] {
+        check_sector(t, sector);
+        otoc_impl(sector, t, dtype, i, j, beta, times, nt, nvec, real_of_col, psi0, opts, F, F_im, Z, stream);
     });
 }
 
@@ -372,17 +518,19 @@ syk_status syk_otoc_unregularized(syk_terms t, syk_dtype dtype, int i, int j, do
                                   hipStream_t stream)
 {
     return guard([&] {
-        check_handle(t);
-        check_dtype(dtype);
-        check_block(t, nvec, real_of_col);
-        syk_krylov_opts o = check_opts(opts);
-        require(i >= 0 && i < t->H.N && j >= 0 && j < t->H.N, "Majorana index out of range");
-        require(i != j, "the OTOC needs i != j");
-        require(std::isfinite(beta) && beta >= 0, "beta must be finite and >= 0");
-        check_ptr(psi0, "psi0");
-        require(F != nullptr, "F is NULL");
-        BlockCtx c(*t, dtype, nvec, real_of_col, stream);
-        otoc_unregularized(c, i, j, beta, times, nt, psi0, o, F, F_im, Z);
+        otoc_unregularized_impl(-1, t, dtype, i, j, beta, times, nt, nvec, real_of_col, psi0, opts, F, F_im, Z, stream);
+    });
+}
+
+syk_status syk_otoc_unregularized_sector(syk_terms t, syk_dtype dtype, int sector, int i, int j, double beta,
+                                         const double* times, int nt, int nvec, const int32_t* real_of_col,
+                                         const void* psi0, const syk_krylov_opts* opts, double* F, double* F_im,
+                                         double* Z, hipStream_t stream)
+{
+    return guard([&] {
+        check_sector(t, sector);
+        otoc_unregularized_impl(sector, t, dtype, i, j, beta, times, nt, nvec, real_of_col, psi0, opts, F, F_im, Z,
+                                stream);
     });
 }
 
@@ -390,17 +538,16 @@ syk_status syk_imag_two_point(syk_terms t, syk_dtype dtype, int i, double beta, 
                               int nvec, const int32_t* real_of_col, const void* psi0, const syk_krylov_opts* opts,
                               double* G, double* Z, hipStream_t stream)
 {
+    return guard([&] { imag_two_point_impl(-1, t, dtype, i, beta, taus, ntau, nvec, real_of_col, psi0, opts, G, Z, stream); });
+}
+
+syk_status syk_imag_two_point_sector(syk_terms t, syk_dtype dtype, int sector, int i, double beta, const double* taus,
+                                     int ntau, int nvec, const int32_t* real_of_col, const void* psi0,
+                                     const syk_krylov_opts* opts, double* G, double* Z, hipStream_t stream)
+{
     return guard([&] {
-        check_handle(t);
-        check_dtype(dtype);
-        check_block(t, nvec, real_of_col);
-        syk_krylov_opts o = check_opts(opts);
-        require(i >= 0 && i < t->H.N, "Majorana index out of range");
-        require(std::isfinite(beta) && beta >= 0, "beta must be finite and >= 0");
-        check_ptr(psi0, "psi0");
-        require(G != nullptr, "G is NULL");
-        BlockCtx c(*t, dtype, nvec, real_of_col, stream);
-        imag_two_point(c, i, beta, taus, ntau, psi0, o, G, Z);
+        check_sector(t, sector);
+        imag_two_point_impl(sector, t, dtype, i, beta, taus, ntau, nvec, real_of_col, psi0, opts, G, Z, stream);
     });
 }
 

@@ -417,7 +417,8 @@ void launch_t(const ApplyPlan& P, const KTerms<R>& T, const QApplyChunk* chunks,
 
 // Chunks and class-sorted records of the apply kernel for tiles of 2^tile_bits
 // rows, 2^lane_bits threads and elements of esz bytes.  masks must be sorted by
-// x; QUAD masks that flip no row bit inside a tile go to the far list.
+// x; QUAD masks that neither flip nor sign-depend on a row bit inside a tile go
+// to the far list.
 void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int lane_bits, uint32_t esz,
                         std::vector<QApplyChunk>& chunks, std::vector<QRec>& recs, std::vector<FarRec>& far)
 {
@@ -436,7 +437,8 @@ void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int la
         const uint32_t xh = masks[i].x >> tile_bits;
         while (i < masks.size() && (masks[i].x >> tile_bits) == xh && mem.size() < (size_t)apply_chunk_masks(esz)) {
             const MaskRec& m = masks[i];
-            if (type_of(m) == MASK_QUAD && (m.x & row_mask) == 0u)
+            // far: coefficient constant over a tile (no flipped qubit and no Z-string bit inside it)
+            if (type_of(m) == MASK_QUAD && (m.x & row_mask) == 0u && (m.zbase & row_mask) == 0u)
                 far.push_back({m.x >> tile_bits, m.qpack, m.zbase, m.type_tab & 0x0fffffffu});
             else
                 mem.push_back((uint32_t)i);
@@ -520,8 +522,8 @@ std::vector<MaskRec> layout_masks(const std::vector<MaskRec>& masks, int M, int 
         r.zbase = rotate_bits(m.zbase, M, tb);
         r.qpack = 0;   // table index bit q stays bit q; only its qubit moves
         for (int q = 0; q < 4; ++q) {
-            const int b = (int)mask_q(m.qpack, q);
-            r.qpack |= (uint32_t)(b >= tb ? b - tb : b + (M - tb)) << (8 * q);
+            const int b = (int)mask_q(m.qpack, q);   // 31: placeholder of an unused index bit
+            r.qpack |= (uint32_t)(b == 31 ? 31 : b >= tb ? b - tb : b + (M - tb)) << (8 * q);
         }
         out.push_back(r);
     }

@@ -78,12 +78,14 @@ struct ApplyPlan {
 
 ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune);
 
-// The plan for a handle, honouring its syk_set_apply_tuning settings.
-inline ApplyPlan plan_for(const syk_terms_s& h, int nvec, syk_dtype dtype)
+// The plan for a handle's tables of M qubits, honouring its
+// syk_set_apply_tuning settings.
+inline ApplyPlan plan_for(const syk_terms_s& h, int M, int nvec, syk_dtype dtype)
 {
     ApplyTuning t{h.tune_tile_bits, h.tune_threads, h.tune_xcd};
-    return plan_apply(h.H.M, nvec, dtype, h.tuned ? &t : nullptr);
+    return plan_apply(M, nvec, dtype, h.tuned ? &t : nullptr);
 }
+inline ApplyPlan plan_for(const syk_terms_s& h, int nvec, syk_dtype dtype) { return plan_for(h, h.H.M, nvec, dtype); }
 
 struct ApplyPlan;
 // Device mask records for a single-vector launch shape (built on first use).

@@ -72,6 +72,18 @@ struct syk_terms_s {
     unsigned upload_slot = 0;       // ring position of small coefficient uploads
     std::map<int, std::unique_ptr<syk::DevBuf>> grad_chunks;   // per tile_bits
     std::map<int, int> grad_nchunks, grad_nmembers;
+    // H restricted to each fermion-parity sector, built on first use
+    struct Sector {
+        syk::TermTables host;
+        syk::DeviceTerms dev;
+        syk::HamiltonianDev H;
+    };
+    std::unique_ptr<Sector> sectors[2];
     bool tuned = false;             // apply_H launch shape set by syk_set_apply_tuning
     int tune_tile_bits = 0, tune_threads = 0, tune_xcd = 1;
 };
+
+namespace syk {
+// Tables of the sector-s Hamiltonian of a handle (built on first use).
+const HamiltonianDev& sector_ham(syk_terms_s& h, int s);
+}  // namespace syk

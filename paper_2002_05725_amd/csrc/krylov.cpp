@@ -12,13 +12,25 @@
 
 namespace syk {
 
-BlockCtx::BlockCtx(syk_terms_s& h_, syk_dtype dt, int nvec_, const int32_t* real, hipStream_t s)
-    : h(h_), dtype(dt), nvec(nvec_), real_of_col(real), stream(s),
-      plan(plan_for(h_, nvec_, dt)), ops(h_, dt, (int64_t)1 << h_.H.M, nvec_, s)
+BlockCtx::BlockCtx(syk_terms_s& h_, syk_dtype dt, int nvec_, const int32_t* real, hipStream_t s, int sector)
+    : h(h_), dtype(dt), nvec(nvec_), real_of_col(real), stream(s), sector0(sector),
+      Hact(sector < 0 ? &h_.H : &sector_ham(h_, sector)), plan(plan_for(h_, Hact->M, nvec_, dt)),
+      ops(h_, dt, (int64_t)1 << Hact->M, nvec_, s)
 {
 }
 
-void BlockCtx::apply_H(const void* in, void* out) { launch_apply_h(h.H, dtype, nvec, real_of_col, in, out, plan, stream); }
+void BlockCtx::apply_H(const void* in, void* out) { launch_apply_h(*Hact, dtype, nvec, real_of_col, in, out, plan, stream); }
+
+void BlockCtx::at(int s)
+{
+    if (sector0 >= 0) Hact = &sector_ham(h, s);
+}
+
+void BlockCtx::majorana(int a, int s_in, const void* in, void* out)
+{
+    if (s_in < 0) ops.majorana(a, in, out);
+    else ops.majorana_sector(a, Hact->M, s_in, in, out);
+}
 
 // Cyclic Jacobi rotations; n <= 64.  Converges to full FP64 accuracy.
 void symmetric_eig(int n, std::vector<double>& a, std::vector<double>& w, std::vector<double>& v)

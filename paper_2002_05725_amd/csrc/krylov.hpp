@@ -9,19 +9,29 @@
 
 namespace syk {
 
-// Everything a propagation needs for one block of columns.
+// Everything a propagation needs for one block of columns.  With sector >= 0
+// the states live in a fermion-parity sector (2^(M-1) rows): apply_H uses the
+// tables of the active sector (at()), and chi maps a sector to the other.
 struct BlockCtx {
     syk_terms_s& h;
     syk_dtype dtype;
     int nvec;
     const int32_t* real_of_col;   // host or NULL
     hipStream_t stream;
+    int sector0;                  // sector of the input states, -1 for the full space
+    const HamiltonianDev* Hact;   // tables apply_H uses
     ApplyPlan plan;
     VecOps ops;
 
-    BlockCtx(syk_terms_s& h_, syk_dtype dt, int nvec_, const int32_t* real, hipStream_t s);
-    int64_t dim() const { return (int64_t)1 << h.H.M; }
+    BlockCtx(syk_terms_s& h_, syk_dtype dt, int nvec_, const int32_t* real, hipStream_t s, int sector = -1);
+    int64_t dim() const { return (int64_t)1 << Hact->M; }
     void apply_H(const void* in, void* out);
+    // apply_H acts in sector s from now on (nothing in the full space)
+    void at(int s);
+    // out = chi_a in for states of sector s_in (-1: the full space); out is in sector 1 - s_in
+    void majorana(int a, int s_in, const void* in, void* out);
+    // the sector opposite to s (-1 stays -1)
+    static int other(int s) { return s < 0 ? -1 : 1 - s; }
 };
 
 struct KrylovStats {

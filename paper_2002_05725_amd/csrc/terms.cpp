@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <unordered_map>
 
 namespace syk {
@@ -244,6 +245,120 @@ std::vector<Group> make_groups(const std::vector<MaskRec>& masks, int tile_bits,
     for (Group& c : g)
         if (c.n_quad == 0) c.quad_first = 0;
     return g;
+}
+
+}  // namespace syk
+
+namespace syk {
+
+// Tables of H restricted to one fermion-parity sector (SI, section
+// "Jordan-Wigner transformation": H conserves the parity of the qubit string,
+// so it is block-diagonal in the two sectors).  A sector-s state keeps the
+// rows r with popcount(r) = s (mod 2), indexed by u = r without its top qubit
+// t = M-1, whose bit is then parity(u) ^ s.  Every flip mask has even weight,
+// so x acts on u as x & low.  A dependence on the implied bit b = parity(u)^s
+// becomes a Z string over all of u: (-1)^b = (-1)^s (-1)^{|u & low|}.
+//  - QUAD masks without t: unchanged.  With q3 = t the table index bit 3 is b:
+//    T[i | b<<3] = A[i] + (-1)^b B[i] gives two masks flipping q0..q2 with
+//    tables A and (-1)^s (-1)^{|i|} B (bit 3 of the index unused, qubit 31 as
+//    a never-set placeholder), Z strings zbase and (zbase ^ low) minus x.
+//  - PAIR masks with q1 = t: the terms with e1 = 0 do not see b, those with
+//    e1 = 1 carry (-1)^{1 + b}: two masks flipping q0 (placeholder 31 for q1,
+//    which the kernel reads as bit 0, flipping e1 = 1 terms once), Z strings
+//    zbase and zbase ^ low.  Otherwise the linear forms' term w_{e,t} r_t =
+//    w/2 - (w/2)(-1)^s (-1)^{|u & low|} moves w/2 into W_e and leaves a second
+//    mask with constant forms -(-1)^s w_{e,t}/2 and Z string zbase ^ low.
+//  - DIAG terms with Z on t: Z string (dz & low) ^ low, coefficient times (-1)^s.
+void build_sector_tables(const TermTables& F, int s, TermTables& out)
+{
+    const int M = F.M, R = F.n_real;
+    if (M < 3) throw Error(SYK_EINVAL, "parity sectors need N >= 6");
+    const int tq = M - 1;
+    const uint32_t low = (1u << tq) - 1u;
+    const double ss = (s & 1) ? -1.0 : 1.0;
+    out = TermTables{};
+    out.N = F.N;
+    out.M = tq;
+    out.n_real = R;
+    out.n_terms = F.n_terms;
+    std::vector<MaskRec> masks;
+    auto add_quad = [&](uint32_t x, uint32_t zb, uint32_t qpack, const std::function<c128(int, int)>& tab) {
+        MaskRec m{x, zb, qpack, (uint32_t)MASK_QUAD << 28 | (uint32_t)out.n_quad};
+        masks.push_back(m);
+        for (int r = 0; r < R; ++r)
+            for (int i = 0; i < 16; ++i) out.tab4.push_back(tab(r, i));
+        out.qinfo.push_back(qpack);
+        out.qinfo.push_back(zb);
+        ++out.n_quad;
+    };
+    const int Wn = M + 1;   // weights per linear form in the full tables
+    auto add_pair = [&](uint32_t x, uint32_t zb, uint32_t qpack, const std::function<c128(int)>& phi,
+                        const std::function<double(int, int, int)>& w /* (r, e, c <= tq; c == tq is W) */) {
+        MaskRec m{x, zb, qpack, (uint32_t)MASK_PAIR << 28 | (uint32_t)out.n_pair};
+        masks.push_back(m);
+        for (int i = 0; i < 16; ++i) out.phi2.push_back(phi(i));
+        for (int r = 0; r < R; ++r)
+            for (int e = 0; e < 4; ++e)
+                for (int c = 0; c <= tq; ++c) out.w2.push_back(w(r, e, c));
+        ++out.n_pair;
+    };
+    for (const MaskRec& m : F.masks) {
+        const uint32_t type = m.type_tab >> 28, tab = m.type_tab & 0x0fffffffu;
+        if (type == MASK_QUAD) {
+            const c128* T = &F.tab4[(size_t)tab * R * 16];
+            if (!((m.x >> tq) & 1u)) {
+                add_quad(m.x, m.zbase, m.qpack, [&](int r, int i) { return T[r * 16 + i]; });
+            } else {
+                if (mask_q(m.qpack, 3) != (uint32_t)tq || (m.zbase >> tq)) throw Error(SYK_EINVAL, "sector: QUAD layout");
+                const uint32_t x = m.x & low;
+                const uint32_t qp = (m.qpack & 0x00ffffffu) | (31u << 24);
+                add_quad(x, m.zbase, qp, [&](int r, int i) {
+                    const c128 a = T[r * 16 + (i & 7)], b = T[r * 16 + ((i & 7) | 8)];
+                    return c128{0.5 * (a.re + b.re), 0.5 * (a.im + b.im)};
+                });
+                add_quad(x, (m.zbase ^ low) & ~x, qp, [&](int r, int i) {
+                    const c128 a = T[r * 16 + (i & 7)], b = T[r * 16 + ((i & 7) | 8)];
+                    const double sg = ss * ((__builtin_popcount((unsigned)(i & 7)) & 1) ? -1.0 : 1.0);
+                    return c128{0.5 * sg * (a.re - b.re), 0.5 * sg * (a.im - b.im)};
+                });
+            }
+        } else if (type == MASK_PAIR) {
+            const c128* P = &F.phi2[(size_t)tab * 16];
+            const double* Wt = &F.w2[(size_t)tab * R * 4 * Wn];
+            auto wf = [&](int r, int e, int c) { return Wt[((size_t)r * 4 + e) * Wn + c]; };
+            if (mask_q(m.qpack, 1) == (uint32_t)tq) {
+                for (int r = 0; r < R; ++r)
+                    for (int e = 0; e < 4; ++e)
+                        if (wf(r, e, tq) != 0.0) throw Error(SYK_EINVAL, "sector: pair on the top qubit");
+                const uint32_t x = m.x & low;
+                const uint32_t qp = (m.qpack & 0xffu) | (31u << 8);
+                auto wsec = [&](int r, int e, int c) { return c == tq ? wf(r, e, M) : wf(r, e, c); };
+                add_pair(x, m.zbase, qp, [&](int i) { return (i & 2) ? c128{0.0, 0.0} : P[i]; }, wsec);
+                add_pair(x, m.zbase ^ low, qp,
+                         [&](int i) { return (i & 2) ? c128{ss * P[i].re, ss * P[i].im} : c128{0.0, 0.0}; }, wsec);
+            } else {
+                add_pair(m.x, m.zbase, m.qpack, [&](int i) { return P[i]; }, [&](int r, int e, int c) {
+                    return c == tq ? wf(r, e, M) + 0.5 * wf(r, e, tq) : wf(r, e, c);
+                });
+                add_pair(m.x, m.zbase ^ low, m.qpack, [&](int i) { return P[i]; }, [&](int r, int e, int c) {
+                    return c == tq ? -0.5 * ss * wf(r, e, tq) : 0.0;
+                });
+            }
+        } else {
+            masks.push_back({0u, 0u, 0u, (uint32_t)MASK_DIAG << 28});
+            out.n_diag = F.n_diag;
+            out.dz.resize(F.n_diag);
+            out.dw.resize((size_t)R * F.n_diag);
+            for (int n = 0; n < F.n_diag; ++n) {
+                const bool top = (F.dz[n] >> tq) & 1u;
+                out.dz[n] = top ? ((F.dz[n] & low) ^ low) : F.dz[n];
+                for (int r = 0; r < R; ++r)
+                    out.dw[(size_t)r * F.n_diag + n] = (top ? ss : 1.0) * F.dw[(size_t)r * F.n_diag + n];
+            }
+        }
+    }
+    std::stable_sort(masks.begin(), masks.end(), [](const MaskRec& a, const MaskRec& b) { return a.x < b.x; });
+    out.masks = std::move(masks);
 }
 
 }  // namespace syk

@@ -105,6 +105,11 @@ void couplings_from_bins(const TermTables& T, const double* bins /* n_bins (re, 
 
 void build_tables(int N, int n_real, const double* J, TermTables& out);
 
+// Tables of H restricted to the fermion-parity sector s (rows with popcount
+// parity s, indexed without their top qubit, whose bit is implied): M - 1
+// qubits, masks over them, no derivative bins.
+void build_sector_tables(const TermTables& full, int s, TermTables& out);
+
 // Device-resident copies of the tables.
 struct DeviceTerms {
     DevBuf masks, tab4_d, tab4_f, qinfo, phi2_d, phi2_f, w2_d, w2_f, dz, dw_d, dw_f;

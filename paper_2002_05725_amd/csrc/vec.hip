@@ -72,6 +72,39 @@ __global__ void __launch_bounds__(RB) k_majorana(const cplx<R>* __restrict__ in,
     }
 }
 
+// chi_a on a parity-sector state (rows u: full row u + 2^top (parity(u) ^ s_in)).
+// For k = a/2 < top the map is the full-space one on u; for k = top the flipped
+// qubit is the implied one, so u maps to itself and the Z string below it covers
+// every bit of u.
+template <typename R>
+__global__ void __launch_bounds__(RB) k_majorana_sector(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
+                                                        Shape S, int a, int top, int s_in)
+{
+    const int64_t col = (int64_t)blockIdx.y * S.D;
+    const int k = a >> 1;
+    const bool implied = (k == top);
+    const uint64_t bit = implied ? 0u : (uint64_t)1 << k;
+    const uint64_t below = implied ? (uint64_t)S.D - 1u : bit - 1u;
+    const R amp = (R)0.70710678118654752440;
+    const int64_t step = (int64_t)gridDim.x * RB;
+    for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < S.D; r += step) {
+        const uint64_t s = (uint64_t)r ^ bit;   // source row
+        const cplx<R> v = in[col + (int64_t)s];
+        int neg = __popcll(s & below) & 1;
+        cplx<R> o;
+        if (a & 1) {             // i (-1)^{s_k} times the Z string
+            neg ^= implied ? ((__popcll(s) & 1) ^ s_in) : (int)((s >> k) & 1);
+            o.re = -amp * v.im;
+            o.im = amp * v.re;
+        } else {
+            o.re = amp * v.re;
+            o.im = amp * v.im;
+        }
+        if (neg) { o.re = -o.re; o.im = -o.im; }
+        out[col + r] = o;
+    }
+}
+
 // partial[bx][k][c] = sum over this workgroup's rows of conj(V_k[r,c]) w[r,c]
 template <typename R>
 __global__ void __launch_bounds__(RB) k_multidot(const cplx<R>* __restrict__ V, int64_t vstride, int K,
@@ -245,6 +278,18 @@ void VecOps::majorana(int a, const void* in, void* out)
         hipLaunchKernelGGL(k_majorana<double>, g, dim3(RB), 0, s_, (const c128*)in, (c128*)out, S, a);
     else
         hipLaunchKernelGGL(k_majorana<float>, g, dim3(RB), 0, s_, (const c64*)in, (c64*)out, S, a);
+    SYK_HIP(hipGetLastError());
+}
+
+void VecOps::majorana_sector(int a, int top, int s_in, const void* in, void* out)
+{
+    if ((a >> 1) > top || top >= 63 || (s_in != 0 && s_in != 1)) throw Error(SYK_EINVAL, "majorana: bad sector arguments");
+    Shape S{dim_, nvec_};
+    dim3 g = grid_of(S, false);
+    if (dt_ == SYK_C128)
+        hipLaunchKernelGGL(k_majorana_sector<double>, g, dim3(RB), 0, s_, (const c128*)in, (c128*)out, S, a, top, s_in);
+    else
+        hipLaunchKernelGGL(k_majorana_sector<float>, g, dim3(RB), 0, s_, (const c64*)in, (c64*)out, S, a, top, s_in);
     SYK_HIP(hipGetLastError());
 }
 

@@ -23,6 +23,9 @@ public:
 
     // out = chi_a in (SI Jordan-Wigner map, with the 2^{-1/2}).
     void majorana(int a, const void* in, void* out);
+    // chi_a between parity sectors: rows u of a sector-s_in state stand for the
+    // full rows u + 2^top (parity(u) ^ s_in); out is in sector 1 - s_in
+    void majorana_sector(int a, int top, int s_in, const void* in, void* out);
     // host [K][nvec]: <V_k | w> per column, V_k = V + k * vec_bytes.
     std::vector<zd> multidot(const void* V, int K, const void* w);
     // host [nvec]: ||a||^2 per column.

@@ -435,3 +435,23 @@ def test_lanczos_ritz_residual_bound():
     assert np.all(gap <= res + 1e-12)
     assert theta[0] >= ev[0] - 1e-12
     assert abs(theta[0] - ev[0]) < 1e-10
+
+
+# ------------------------------------------------------------ parity sectors
+@pytest.mark.parametrize("N", [8, 10, 12])
+def test_sector_rows_split_h_and_majoranas(N):
+    """The two sectors are the rows of each popcount parity; H has no block
+    between them, its spectrum is the union of the two sector spectra, and
+    every Majorana maps each sector into the other."""
+    H = jw.dense_H(N, inputs.couplings(N, 8))
+    r0, r1 = jw.sector_rows(N, 0), jw.sector_rows(N, 1)
+    pc = np.array([bin(int(r)).count("1") for r in range(H.shape[0])])
+    assert sorted(np.concatenate((r0, r1)).tolist()) == list(range(H.shape[0]))
+    assert np.all(pc[r0] % 2 == 0) and np.all(pc[r1] % 2 == 1)
+    assert np.all(np.diff(r0 & ((1 << (N // 2 - 1)) - 1)) == 1)
+    assert np.abs(H[np.ix_(r0, r1)]).max() == 0.0
+    ev = np.linalg.eigvalsh(H)
+    evs = np.sort(np.concatenate((np.linalg.eigvalsh(H[np.ix_(r0, r0)]), np.linalg.eigvalsh(H[np.ix_(r1, r1)]))))
+    assert np.abs(ev - evs).max() < 1e-12
+    for chi in jw.dense_majoranas(N):
+        assert np.abs(chi[np.ix_(r0, r0)]).max() == 0.0 and np.abs(chi[np.ix_(r1, r1)]).max() == 0.0
