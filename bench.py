@@ -167,6 +167,8 @@ def main():
     ap.add_argument("--m", type=int, default=12)
     ap.add_argument("--dt", type=float, default=0.25)
     ap.add_argument("--c64-steps", type=int, default=1)
+    ap.add_argument("--sector-steps", type=int, default=1,
+                    help="time steps of the parity-sector leg (complex128, half-size state; 0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-N", type=int, default=40, help="size of the batched leg (0: skip)")
@@ -242,6 +244,30 @@ def main():
         del p64
         log(f"[bench] c64: {c64['ms_per_step']:.0f} ms/step, apply {a64 * 1e3:.1f} ms")
 
+    sector = None
+    if args.sector_steps > 0:
+        torch.cuda.empty_cache()
+        u_host = inputs.typical_sector_state(N, 0, 1)
+        u = torch.from_numpy(u_host).to(dev)
+        del u_host
+        log(f"[bench] parity sector 0: 1 warmup + {args.sector_steps} timed steps")
+        api.krylov_expmv(T, u, -1j, dt, m=m, dt=dt, sector=0)
+        torch.cuda.synchronize()
+        api.timing_reset()
+        api.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.sector_steps):
+            api.krylov_expmv(T, u, -1j, dt, m=m, dt=dt, sector=0)
+        torch.cuda.synchronize()
+        ws = time.perf_counter() - t0
+        api.timing_enable(False)
+        ns, mss = api.timing_read()
+        api.timing_reset()
+        sector = {"sector": 0, "dim": D // 2, "otoc_time_steps_per_s": args.sector_steps / ws,
+                  "ms_per_step": ws / args.sector_steps * 1e3, "apply_ms": mss / ns}
+        del u
+        log(f"[bench] sector: {sector['ms_per_step']:.0f} ms/step, apply {sector['apply_ms']:.1f} ms")
+
     batched = None
     if args.batch_N > 0:
         torch.cuda.empty_cache()
@@ -296,6 +322,7 @@ def main():
             "traffic_unit": "bytes per apply_H call (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },
         "complex64": c64,
+        "parity_sector": sector,
         "batched": batched,
         "gradient": grad,
         "grad_fwd_ratio": grad["grad_fwd_ratio"] if grad else None,

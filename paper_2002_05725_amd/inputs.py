@@ -82,3 +82,21 @@ def batch_coupling_seed(N: int, r: int) -> int:
 
 def batch_state_seed(N: int, r: int, s: int) -> int:
     return 10 ** 6 + 1000 * N + 2 * r + s
+
+
+def typical_sector_state(N: int, s: int, seed: int) -> np.ndarray:
+    """Typical state of the fermion-parity sector s: the entries of
+    typical_state(N, seed) on the rows of popcount parity s, in the sector
+    order (entry u is the full row u + 2^(M-1) (parity(u) ^ s)), renormalized."""
+    M = N // 2
+    u = np.arange(1 << (M - 1), dtype=np.int64)
+    par = np.zeros_like(u)
+    v = u.copy()
+    while v.any():
+        par ^= v & 1
+        v >>= 1
+    rows = u + ((par ^ (s & 1)) << (M - 1))
+    del u, par, v
+    psi = typical_state(N, seed)[rows]
+    return psi / np.linalg.norm(psi)
+
