@@ -223,7 +223,8 @@ syk_status syk_spectrum_bounds(syk_terms t, syk_dtype dtype, int m, const void* 
  * invariant, in which case the residuals are 0).  A starting vector reaches
  * one copy of each distinct level in exact arithmetic; in floating point
  * copies of degenerate levels can appear late.  Holds m state vectors of
- * workspace (2 <= m <= 1024, 1 <= k <= m).
+ * workspace (2 <= m <= 512, 1 <= k <= m); the host eigen-decomposition of the
+ * m x m projection costs O(m^3).
  */
 syk_status syk_lowest_eigenvalues(syk_terms t, syk_dtype dtype, int m, int k, const void* psi0, double* evals,
                                   double* resid, int* n_found, hipStream_t stream);

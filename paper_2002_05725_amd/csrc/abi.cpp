@@ -571,7 +571,7 @@ syk_status syk_lowest_eigenvalues(syk_terms t, syk_dtype dtype, int m, int k, co
     return guard([&] {
         check_handle(t);
         check_dtype(dtype);
-        require(m >= 2 && m <= 1024, "m must be in [2, 1024]");
+        require(m >= 2 && m <= 512, "m must be in [2, 512]");
         require(k >= 1 && k <= m, "k must be in [1, m]");
         check_ptr(psi0, "psi0");
         require(evals != nullptr && n_found != nullptr, "outputs are NULL");

@@ -32,7 +32,8 @@ void BlockCtx::majorana(int a, int s_in, const void* in, void* out)
     else ops.majorana_sector(a, Hact->M, s_in, in, out);
 }
 
-// Cyclic Jacobi rotations; n <= 64.  Converges to full FP64 accuracy.
+// Cyclic Jacobi rotations on the dense n x n matrix (O(n^3) per sweep, a few
+// sweeps).  Converges to full FP64 accuracy.
 void symmetric_eig(int n, std::vector<double>& a, std::vector<double>& w, std::vector<double>& v)
 {
     v.assign((size_t)n * n, 0.0);
