@@ -16,7 +16,6 @@ namespace syk {
 namespace {
 
 constexpr int RB = 256;    // threads per workgroup
-constexpr int RG = 240;    // workgroups per column of a reduction (fixed for reproducibility)
 constexpr int KC = 8;      // vectors per pass of a multi-vector kernel
 
 struct Shape {
@@ -24,10 +23,15 @@ struct Shape {
     int B;       // columns
 };
 
+// Workgroups per column: about 2048 over the whole block (a few per CU, enough
+// loads in flight to stream at HBM speed), at most 1024 per column.  For
+// reductions this count is a function of the shape only, so the summation
+// order, and the result, do not depend on timing.
 inline dim3 grid_of(const Shape& S, bool reduction)
 {
-    int64_t want = (S.D + RB - 1) / RB;
-    int gx = reduction ? RG : std::max<int64_t>(1, 4096 / std::max(1, S.B));
+    const int64_t want = (S.D + RB - 1) / RB;
+    int gx = reduction ? std::max(32, std::min(1024, 2048 / std::max(1, S.B)))
+                       : (int)std::max<int64_t>(1, 4096 / std::max(1, S.B));
     if (want < gx) gx = (int)want;
     if (gx < 1) gx = 1;
     return dim3(gx, S.B);
