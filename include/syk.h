@@ -301,6 +301,19 @@ syk_status syk_cheb_otoc(syk_terms t, int i, int j, double beta, double t_star, 
 syk_status syk_grad_couplings(syk_terms t, int i, int j, double beta, double t_star, const syk_cheb_opts* opts,
                               const void* psi0, double* F, double* dF_dJ, hipStream_t stream);
 
+/*
+ * The per-coupling reductions of the adjoint gradient on their own:
+ * out[n] = sum_p w[p] Re <g_p| dH/dJ_n |v_p> for every coupling n (host array of
+ * C(N,4) doubles, lexicographic quartet order), where dH/dJ_n is the Majorana
+ * quartet chi_a chi_b chi_c chi_d of coupling n (Eq. 1, Jordan-Wigner form as
+ * in apply_H).  It does not depend on the couplings' values.  g, v: host arrays
+ * of npairs device pointers, each a complex128 vector of the full space
+ * (2^(N/2) elements, 16-byte aligned, not modified); w: host array of npairs
+ * finite weights; 1 <= npairs <= 64.  Synchronises the stream before returning.
+ */
+syk_status syk_coupling_overlaps(syk_terms t, int npairs, const void* const* g, const void* const* v,
+                                 const double* w, double* out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

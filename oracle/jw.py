@@ -107,3 +107,25 @@ def sector_rows(N: int, s: int) -> np.ndarray:
         par ^= v & 1
         v >>= 1
     return u + ((par ^ s) << (M - 1))
+
+
+def quartet_apply(N: int, q, psi: np.ndarray) -> np.ndarray:
+    """chi_i chi_j chi_k chi_l psi for the quartet q = (i, j, k, l), i < j < k < l:
+    the operator multiplying J_ijkl in Eq. 1, applied as four Majoranas (the
+    rightmost acts first), without a matrix."""
+    i, j, k, l = q
+    out = psi
+    for a in (l, k, j, i):
+        out = majorana_apply(N, a, out)
+    return out
+
+
+def coupling_overlaps(N: int, qs, pairs) -> np.ndarray:
+    """For each quartet q in qs: sum_p w_p Re <g_p| chi_i chi_j chi_k chi_l |v_p>,
+    the derivative of sum_p w_p Re <g_p|H|v_p> with respect to J_ijkl (Eq. 1 is
+    linear in the couplings).  pairs: (g, v, w) triples."""
+    out = np.zeros(len(qs))
+    for n, q in enumerate(qs):
+        for g, v, w in pairs:
+            out[n] += w * np.vdot(g, quartet_apply(N, q, v)).real
+    return out

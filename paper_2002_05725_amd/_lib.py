@@ -76,6 +76,7 @@ _SIGS = {
     "syk_spectrum_bounds": (_i, [_vp, _i, _i, _vp, ctypes.POINTER(_d), ctypes.POINTER(_d), _vp]),
     "syk_cheb_otoc": (_i, [_vp, _i, _i, _d, _d, ctypes.POINTER(ChebOpts), _vp, ctypes.POINTER(_d), _vp]),
     "syk_grad_couplings": (_i, [_vp, _i, _i, _d, _d, ctypes.POINTER(ChebOpts), _vp, ctypes.POINTER(_d), _vp, _vp]),
+    "syk_coupling_overlaps": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
 }
 
 

@@ -311,6 +311,28 @@ def cheb_otoc(terms: Terms, i: int, j: int, beta: float, t_star: float, psi0: to
     return F.value
 
 
+def coupling_overlaps(terms: Terms, pairs):
+    """sum_p w_p Re <g_p| dH/dJ_n |v_p> for every coupling n, as a numpy array of
+    C(N,4) (syk_coupling_overlaps).  pairs: up to 64 (g, v, w) with g, v
+    complex128 full-space states on the device."""
+    pairs = list(pairs)
+    if not 1 <= len(pairs) <= 64:
+        raise ValueError("need 1 to 64 pairs")
+    for g, v, _ in pairs:
+        for x, name in ((g, "g"), (v, "v")):
+            _check_state(x, terms.dim, name)
+            if x.dtype != torch.complex128 or x.dim() != 1:
+                raise ValueError(f"{name}: one complex128 state per pair")
+    n = len(pairs)
+    gp = (ctypes.c_void_p * n)(*[g.data_ptr() for g, _, _ in pairs])
+    vp = (ctypes.c_void_p * n)(*[v.data_ptr() for _, v, _ in pairs])
+    w = np.array([float(x) for _, _, x in pairs], dtype=np.float64)
+    out = np.empty(terms.n_terms, dtype=np.float64)
+    check(lib().syk_coupling_overlaps(terms.handle, n, ctypes.cast(gp, ctypes.c_void_p), ctypes.cast(vp, ctypes.c_void_p),
+                                      _ptr(w), _ptr(out), _stream()), "syk_coupling_overlaps")
+    return out
+
+
 def grad_couplings(terms: Terms, i: int, j: int, beta: float, t_star: float, psi0: torch.Tensor, opts: ChebOpts):
     """(F, dF/dJ as a numpy array of C(N,4)) by the reverse sweep (syk_grad_couplings)."""
     _check_state(psi0, terms.dim, "psi0")

@@ -615,4 +615,33 @@ syk_status syk_grad_couplings(syk_terms t, int i, int j, double beta, double t_s
     });
 }
 
+syk_status syk_coupling_overlaps(syk_terms t, int npairs, const void* const* g, const void* const* v,
+                                 const double* w, double* out, hipStream_t stream)
+{
+    return guard([&] {
+        check_handle(t);
+        require(npairs >= 1 && npairs <= 64, "npairs must be in [1, 64]");
+        require(g != nullptr && v != nullptr && w != nullptr && out != nullptr, "g, v, w or out is NULL");
+        std::vector<const void*> gv(npairs), vv(npairs);
+        std::vector<double> wv(npairs);
+        for (int p = 0; p < npairs; ++p) {
+            check_ptr(g[p], "g[p]");
+            check_ptr(v[p], "v[p]");
+            require(std::isfinite(w[p]), "weights must be finite");
+            gv[p] = g[p];
+            vv[p] = v[p];
+            wv[p] = w[p];
+        }
+        BlockCtx c(*t, SYK_C128, 1, nullptr, stream);
+        const TermTables& T = t->host;
+        double* bins = (double*)t->ws.get("overlap_bins", T.n_bins * 2 * sizeof(double));
+        SYK_HIP(hipMemsetAsync(bins, 0, T.n_bins * 2 * sizeof(double), c.stream));
+        grad_bins(*t, gv, vv, wv, bins, c.stream);
+        std::vector<double> hb(T.n_bins * 2);
+        SYK_HIP(hipMemcpyAsync(hb.data(), bins, hb.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        SYK_HIP(hipStreamSynchronize(c.stream));
+        couplings_from_bins(T, hb.data(), out);
+    });
+}
+
 }  // extern "C"

@@ -379,6 +379,8 @@ __global__ void __launch_bounds__(256) k_transpose(const cplx<R>* __restrict__ s
     }
 }
 
+}  // namespace
+
 void launch_transpose(syk_dtype dtype, const void* src, void* dst, int log_h, int log_w, int ncols, uint64_t dim,
                       bool add, hipStream_t s)
 {
@@ -397,6 +399,8 @@ void launch_transpose(syk_dtype dtype, const void* src, void* dst, int log_h, in
     }
     SYK_HIP(hipGetLastError());
 }
+
+namespace {
 
 template <typename R>
 void launch_t(const ApplyPlan& P, const KTerms<R>& T, const QApplyChunk* chunks, const QRec* rec, KLayout L,
@@ -496,6 +500,32 @@ inline uint32_t rotate_bits(uint32_t v, int M, int s)
     return (v >> s) | ((v & ((1u << s) - 1u)) << (M - s));
 }
 
+}  // namespace
+
+bool quad_in_rotated(const MaskRec& m, int M, int tb)
+{
+    if ((m.type_tab >> 28) != MASK_QUAD) return false;
+    const uint32_t row_mask = (1u << tb) - 1u;
+    const int out_a = __builtin_popcount(m.x & ~row_mask);
+    const int out_b = __builtin_popcount(rotate_bits(m.x, M, tb) & ~row_mask);
+    return out_b < out_a;
+}
+
+MaskRec rotate_mask(const MaskRec& m, int M, int tb)
+{
+    MaskRec r = m;
+    r.x = rotate_bits(m.x, M, tb);
+    r.zbase = rotate_bits(m.zbase, M, tb);
+    r.qpack = 0;   // table index bit q stays bit q; only its qubit moves
+    for (int q = 0; q < 4; ++q) {
+        const int b = (int)mask_q(m.qpack, q);   // 31: placeholder of an unused index bit
+        r.qpack |= (uint32_t)(b == 31 ? 31 : b >= tb ? b - tb : b + (M - tb)) << (8 * q);
+    }
+    return r;
+}
+
+namespace {
+
 // Masks of one layout, in that layout's row coordinates and sorted by x.  With
 // two layouts, a QUAD mask goes to the rotated layout (1) when fewer of its
 // flipped qubits lie outside a tile there; everything else stays in layout 0.
@@ -504,32 +534,16 @@ inline uint32_t rotate_bits(uint32_t v, int M, int s)
 std::vector<MaskRec> layout_masks(const std::vector<MaskRec>& masks, int M, int tb, bool two, int layout)
 {
     std::vector<MaskRec> out;
-    const uint32_t row_mask = (1u << tb) - 1u;
     for (const MaskRec& m : masks) {
-        int in_b = 0;
-        if (two && (m.type_tab >> 28) == MASK_QUAD) {
-            const int out_a = __builtin_popcount(m.x & ~row_mask);
-            const int out_b = __builtin_popcount(rotate_bits(m.x, M, tb) & ~row_mask);
-            in_b = out_b < out_a;
-        }
+        const int in_b = two && quad_in_rotated(m, M, tb);
         if (in_b != layout) continue;
-        if (layout == 0) {
-            out.push_back(m);
-            continue;
-        }
-        MaskRec r = m;
-        r.x = rotate_bits(m.x, M, tb);
-        r.zbase = rotate_bits(m.zbase, M, tb);
-        r.qpack = 0;   // table index bit q stays bit q; only its qubit moves
-        for (int q = 0; q < 4; ++q) {
-            const int b = (int)mask_q(m.qpack, q);   // 31: placeholder of an unused index bit
-            r.qpack |= (uint32_t)(b == 31 ? 31 : b >= tb ? b - tb : b + (M - tb)) << (8 * q);
-        }
-        out.push_back(r);
+        out.push_back(layout == 0 ? m : rotate_mask(m, M, tb));
     }
     std::stable_sort(out.begin(), out.end(), [](const MaskRec& a, const MaskRec& b) { return a.x < b.x; });
     return out;
 }
+
+}  // namespace
 
 // Mask records for launch shape (tile_bits, nt), in mask order.
 std::vector<KRec> build_krecs(const std::vector<MaskRec>& masks, const std::vector<uint64_t>& bin_off, int tile_bits,
@@ -566,8 +580,6 @@ std::vector<KRec> build_krecs(const std::vector<MaskRec>& masks, const std::vect
     }
     return out;
 }
-
-}  // namespace
 
 const KRec* krecs_for(const HamiltonianDev& H, const ApplyPlan& P)
 {

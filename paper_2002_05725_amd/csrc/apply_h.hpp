@@ -91,6 +91,26 @@ struct ApplyPlan;
 // Device mask records for a single-vector launch shape (built on first use).
 const KRec* krecs_for(const HamiltonianDev& H, const ApplyPlan& P);
 
+// Mask records for launch shape (tile_bits, nt), one per mask of `masks` in
+// its order; pad[0] = bin_off[i].
+std::vector<KRec> build_krecs(const std::vector<MaskRec>& masks, const std::vector<uint64_t>& bin_off, int tile_bits,
+                              int nt);
+
+// Second row layout: row bits rotated right by tb (bit b -> b - tb mod M), so
+// that the high qubits of the natural layout become the low bits of a tile.
+// quad_in_rotated: a QUAD mask with fewer flipped qubits outside a tile there
+// than in the natural layout (false for every other mask type).  rotate_mask:
+// the same mask in rotated row coordinates (x, zbase and the qubit of every
+// table index bit relabelled; coefficients unchanged).
+bool quad_in_rotated(const MaskRec& m, int M, int tb);
+MaskRec rotate_mask(const MaskRec& m, int M, int tb);
+
+// dst[c] = src[c] viewed as a [2^log_h] x [2^log_w] row-major matrix and
+// transposed (with add: dst[c] += ...), for ncols columns of dim elements.
+// For log_h = M - tb, log_w = tb this moves every row to its rotated index.
+void launch_transpose(syk_dtype dtype, const void* src, void* dst, int log_h, int log_w, int ncols, uint64_t dim,
+                      bool add, hipStream_t s);
+
 // out = H psi for nvec columns stored one after another; real_of_col: host array or NULL.
 void launch_apply_h(const HamiltonianDev& H, syk_dtype dtype, int nvec, const int32_t* real_of_col,
                     const void* psi, void* out, const ApplyPlan& P, hipStream_t s);

@@ -124,8 +124,10 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
                                                     const uint32_t* __restrict__ local,
                                                     const GRec* __restrict__ grec,
                                                     const uint32_t* __restrict__ dz, GLayout L,
-                                                    const c128* const* __restrict__ gs,
-                                                    const c128* const* __restrict__ vs,
+                                                    const c128* const* __restrict__ gs_nat,
+                                                    const c128* const* __restrict__ vs_nat,
+                                                    const c128* const* __restrict__ gs_rot,
+                                                    const c128* const* __restrict__ vs_rot,
                                                     const double* __restrict__ wts, double* __restrict__ partial)
 {
     constexpr int KB = ilog2c(RPT);
@@ -151,6 +153,9 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
 
     for (int ch = (int)sg; ch < L.n_chunks; ch += (int)L.chunk_groups) {
         const GChunk C = chunks[ch];
+        // the pair vectors in the chunk's row layout
+        const c128* const* __restrict__ gs = C.layout ? gs_rot : gs_nat;
+        const c128* const* __restrict__ vs = C.layout ? vs_rot : vs_nat;
         for (uint32_t e = tid; e < 2 * C.bin_count; e += nt) bins[e] = 0.0;
         for (uint32_t tile = tg; tile < L.n_tiles; tile += L.tile_groups) {
             const uint32_t base = tile << L.tile_bits;
@@ -356,8 +361,8 @@ __global__ void k_bins_reduce(const double* __restrict__ partial, int nblk, uint
 
 }  // namespace
 
-GradChunks make_grad_chunks(const std::vector<MaskRec>& masks, const std::vector<uint64_t>& bin_off,
-                            uint64_t n_bins, int tile_bits, int lane_bits)
+GradChunks make_grad_chunks(const std::vector<MaskRec>& masks, const std::vector<uint8_t>& layout_of,
+                            const std::vector<uint64_t>& bin_off, uint64_t n_bins, int tile_bits, int lane_bits)
 {
     const uint32_t row_mask = (1u << tile_bits) - 1u;
     const uint32_t lane_mask = (1u << lane_bits) - 1u;
@@ -369,7 +374,13 @@ GradChunks make_grad_chunks(const std::vector<MaskRec>& masks, const std::vector
         std::vector<uint32_t> mem;
     };
     std::vector<Build> near, far;
-    for (uint32_t i = 0; i < (uint32_t)masks.size(); ++i) {
+    // each layout's masks in x order (consecutive masks of a chunk share x >> tile_bits)
+    std::vector<uint32_t> order(masks.size());
+    for (uint32_t i = 0; i < (uint32_t)masks.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        return layout_of[a] != layout_of[b] ? layout_of[a] < layout_of[b] : masks[a].x < masks[b].x;
+    });
+    for (const uint32_t i : order) {
         const uint32_t type = masks[i].type_tab >> 28;
         const uint32_t xh = masks[i].x >> tile_bits;
         const uint64_t nb = nbins(i);
@@ -377,13 +388,14 @@ GradChunks make_grad_chunks(const std::vector<MaskRec>& masks, const std::vector
         const bool accm = type != MASK_QUAD;
         const bool is_far = type != MASK_DIAG && (masks[i].x & row_mask) == 0u;
         std::vector<Build>& out = is_far ? far : near;
-        const bool same = !out.empty() && (is_far || out.back().c.x_high == xh);
+        const bool same = !out.empty() && out.back().c.layout == layout_of[i] && (is_far || out.back().c.x_high == xh);
         if (!same || out.back().c.count == (uint32_t)kChunkMasks ||
             out.back().c.bin_count + nb > (uint64_t)kGradBinCap ||
             (accm && out.back().c.n_acc == (uint32_t)kGradAccMasks)) {
             Build b{};
             b.c.x_high = is_far ? 0u : xh;
             b.c.far = is_far ? 1u : 0u;
+            b.c.layout = layout_of[i];
             out.push_back(b);
         }
         Build& b = out.back();
@@ -465,28 +477,40 @@ void grad_bins(syk_terms_s& h, const std::vector<const void*>& g, const std::vec
     const ApplyTuning tune{10, 256, 1};
     const ApplyPlan P = plan_apply(H.M, 1, SYK_C128, &tune);
     require(P.nt <= 256, "gradient: launch shape");
-    const KRec* krec = krecs_for(H, P);
-    // chunk records, member list, LDS bin offsets and QUAD member records in one device buffer
-    auto it = h.grad_chunks.find(P.tile_bits);
+    const bool two = P.two_layouts != 0;
+    // mask records, chunk records, member list, LDS bin offsets and QUAD member
+    // records in one device buffer
+    const int key = P.tile_bits * 2 + (two ? 1 : 0);
+    auto it = h.grad_chunks.find(key);
     if (it == h.grad_chunks.end()) {
-        const GradChunks c = make_grad_chunks(T.masks, T.bin_off, T.n_bins, P.tile_bits, P.lb);
-        const size_t cb = c.chunks.size() * sizeof(GChunk), mb = c.members.size() * sizeof(uint32_t);
-        const size_t gb = c.grec.size() * sizeof(GRec);
+        std::vector<MaskRec> lm(T.masks);
+        std::vector<uint8_t> lay(T.masks.size(), 0);
+        if (two)
+            for (size_t i = 0; i < lm.size(); ++i)
+                if (quad_in_rotated(T.masks[i], H.M, P.tile_bits)) {
+                    lm[i] = rotate_mask(T.masks[i], H.M, P.tile_bits);
+                    lay[i] = 1;
+                }
+        const std::vector<KRec> kr = build_krecs(lm, T.bin_off, P.tile_bits, P.nt);
+        const GradChunks c = make_grad_chunks(lm, lay, T.bin_off, T.n_bins, P.tile_bits, P.lb);
+        const size_t kb = kr.size() * sizeof(KRec), cb = c.chunks.size() * sizeof(GChunk);
+        const size_t gb = c.grec.size() * sizeof(GRec), mb = c.members.size() * sizeof(uint32_t);
         std::unique_ptr<DevBuf> b(new DevBuf());
-        b->ensure(cb + gb + 2 * mb);
+        b->ensure(kb + cb + gb + 2 * mb);
         char* d = static_cast<char*>(b->p);
-        SYK_HIP(hipMemcpy(d, c.chunks.data(), cb, hipMemcpyHostToDevice));
-        SYK_HIP(hipMemcpy(d + cb, c.grec.data(), gb, hipMemcpyHostToDevice));
-        SYK_HIP(hipMemcpy(d + cb + gb, c.members.data(), mb, hipMemcpyHostToDevice));
-        SYK_HIP(hipMemcpy(d + cb + gb + mb, c.local.data(), mb, hipMemcpyHostToDevice));
-        h.grad_nchunks[P.tile_bits] = (int)c.chunks.size();
-        h.grad_nmembers[P.tile_bits] = (int)c.members.size();
-        it = h.grad_chunks.emplace(P.tile_bits, std::move(b)).first;
+        SYK_HIP(hipMemcpy(d, kr.data(), kb, hipMemcpyHostToDevice));
+        SYK_HIP(hipMemcpy(d + kb, c.chunks.data(), cb, hipMemcpyHostToDevice));
+        SYK_HIP(hipMemcpy(d + kb + cb, c.grec.data(), gb, hipMemcpyHostToDevice));
+        SYK_HIP(hipMemcpy(d + kb + cb + gb, c.members.data(), mb, hipMemcpyHostToDevice));
+        SYK_HIP(hipMemcpy(d + kb + cb + gb + mb, c.local.data(), mb, hipMemcpyHostToDevice));
+        h.grad_nchunks[key] = (int)c.chunks.size();
+        h.grad_nmembers[key] = (int)c.members.size();
+        it = h.grad_chunks.emplace(key, std::move(b)).first;
     }
     GLayout L{};
     L.tile_bits = P.tile_bits;
     L.n_tiles = (uint32_t)(((uint64_t)1 << H.M) >> P.tile_bits);
-    L.n_chunks = h.grad_nchunks[P.tile_bits];
+    L.n_chunks = h.grad_nchunks[key];
     L.M = H.M;
     L.n_diag = H.n_diag;
     L.n_bins = T.n_bins;
@@ -496,38 +520,59 @@ void grad_bins(syk_terms_s& h, const std::vector<const void*>& g, const std::vec
     L.tile_groups = (uint32_t)nblk;
     L.chunk_groups = (uint32_t)std::max(1, std::min(L.n_chunks, 2048 / nblk));
 
+    // rotated copies of the pair vectors for the masks of the second layout
+    const uint64_t dim = (uint64_t)1 << H.M;
+    std::vector<const void*> gr(npairs), vr(npairs);
+    for (int p = 0; p < npairs; ++p) {
+        gr[p] = g[p];
+        vr[p] = v[p];
+        if (!two) continue;
+        void* a = h.ws.get("grad_rot_g" + std::to_string(p), dim * sizeof(c128));
+        void* b = h.ws.get("grad_rot_v" + std::to_string(p), dim * sizeof(c128));
+        launch_transpose(SYK_C128, g[p], a, H.M - P.tile_bits, P.tile_bits, 1, dim, false, st);
+        launch_transpose(SYK_C128, v[p], b, H.M - P.tile_bits, P.tile_bits, 1, dim, false, st);
+        gr[p] = a;
+        vr[p] = b;
+    }
+
     // pointer lists and weights: one small synchronous upload.  The list is
     // padded to a multiple of kGradPairsPerStage with copies of pair 0 of
     // weight 0 (their products are exact zeros).
     const int np = (npairs + kGradPairsPerStage - 1) / kGradPairsPerStage * kGradPairsPerStage;
     L.npairs = np;
-    std::vector<uint64_t> host(3 * (size_t)np);
+    std::vector<uint64_t> host(5 * (size_t)np);
     for (int p = 0; p < np; ++p) {
         const int q = p < npairs ? p : 0;
         host[p] = (uint64_t)(uintptr_t)g[q];
         host[np + p] = (uint64_t)(uintptr_t)v[q];
+        host[2 * np + p] = (uint64_t)(uintptr_t)gr[q];
+        host[3 * np + p] = (uint64_t)(uintptr_t)vr[q];
         double wp = p < npairs ? w[p] : 0.0;
-        std::memcpy(&host[2 * np + p], &wp, sizeof(double));
+        std::memcpy(&host[4 * np + p], &wp, sizeof(double));
     }
     void* dlist = h.ws.get("grad_lists", host.size() * sizeof(uint64_t));
     SYK_HIP(hipMemcpyAsync(dlist, host.data(), host.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
     SYK_HIP(hipStreamSynchronize(st));
     const c128* const* gl = (const c128* const*)dlist;
     const c128* const* vl = gl + np;
-    const double* wl = (const double*)(gl + 2 * np);
+    const c128* const* glr = gl + 2 * np;
+    const c128* const* vlr = gl + 3 * np;
+    const double* wl = (const double*)(gl + 4 * np);
 
     double* partial = (double*)h.ws.get("grad_partial", (size_t)nblk * T.n_bins * 2 * sizeof(double));
     const size_t lds = (size_t)kGradPairsPerStage * ((size_t)1 << P.tile_bits) * sizeof(c128) +
                        (size_t)kGradBinCap * 2 * sizeof(double) + (size_t)kChunkMasks * sizeof(uint32_t);
-    const GChunk* chunks = it->second->as<GChunk>();
+    const KRec* krec = it->second->as<KRec>();
+    const GChunk* chunks = reinterpret_cast<const GChunk*>(krec + T.masks.size());
     const GRec* grec = reinterpret_cast<const GRec*>(chunks + L.n_chunks);
-    const uint32_t* members = reinterpret_cast<const uint32_t*>(grec + h.grad_nmembers[P.tile_bits]);
-    const uint32_t* local = members + h.grad_nmembers[P.tile_bits];
+    const uint32_t* members = reinterpret_cast<const uint32_t*>(grec + h.grad_nmembers[key]);
+    const uint32_t* local = members + h.grad_nmembers[key];
+    const dim3 grid(nblk * L.chunk_groups), block(P.nt);
     switch (P.rpt) {
-    case 1: hipLaunchKernelGGL(k_grad_bins<1>, dim3(nblk * L.chunk_groups), dim3(P.nt), lds, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, wl, partial); break;
-    case 2: hipLaunchKernelGGL(k_grad_bins<2>, dim3(nblk * L.chunk_groups), dim3(P.nt), lds, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, wl, partial); break;
-    case 4: hipLaunchKernelGGL(k_grad_bins<4>, dim3(nblk * L.chunk_groups), dim3(P.nt), lds, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, wl, partial); break;
-    case 8: hipLaunchKernelGGL(k_grad_bins<8>, dim3(nblk * L.chunk_groups), dim3(P.nt), lds, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, wl, partial); break;
+    case 1: hipLaunchKernelGGL(k_grad_bins<1>, grid, block, lds, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, glr, vlr, wl, partial); break;
+    case 2: hipLaunchKernelGGL(k_grad_bins<2>, grid, block, lds, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, glr, vlr, wl, partial); break;
+    case 4: hipLaunchKernelGGL(k_grad_bins<4>, grid, block, lds, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, glr, vlr, wl, partial); break;
+    case 8: hipLaunchKernelGGL(k_grad_bins<8>, grid, block, lds, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, glr, vlr, wl, partial); break;
     default: throw Error(SYK_EUNSUPPORTED, "gradient: launch shape");
     }
     SYK_HIP(hipGetLastError());

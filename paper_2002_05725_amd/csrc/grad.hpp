@@ -18,9 +18,11 @@ constexpr int kGradPairsPerStage = 2;   // (g, v) pairs whose source tiles are s
 // x >> tile_bits (one staged source tile); their QUAD members come first,
 // sorted by row class (mask_classes.hpp) with cnt[] masks per class.  A far
 // chunk holds QUAD / PAIR masks that flip no row bit inside a tile, each
-// reading its own source tile straight from global memory.
+// reading its own source tile straight from global memory.  All members of a
+// chunk run in one row layout (0: natural, 1: rotated, apply_h.hpp), in whose
+// coordinates their records are given.
 struct alignas(16) GChunk {
-    uint32_t x_high, first, count, bin_count, n_acc, far, n_quad, pad;
+    uint32_t x_high, first, count, bin_count, n_acc, far, n_quad, layout;
     uint32_t acc[kGradAccMasks];
     uint32_t cnt[8];   // QUAD members per class, one byte per class
 };
@@ -41,8 +43,10 @@ struct GradChunks {
     std::vector<GRec> grec;          // per member (zero for all but near QUAD members)
 };
 
-GradChunks make_grad_chunks(const std::vector<MaskRec>& masks, const std::vector<uint64_t>& bin_off,
-                            uint64_t n_bins, int tile_bits, int lane_bits);
+// masks: every mask in mask order, in the coordinates of its layout
+// (layout_of[i]); members index this list.
+GradChunks make_grad_chunks(const std::vector<MaskRec>& masks, const std::vector<uint8_t>& layout_of,
+                            const std::vector<uint64_t>& bin_off, uint64_t n_bins, int tile_bits, int lane_bits);
 
 // out = b (w - gamma y) + s z + c x ; acc += ca out.  Null pointers drop their term.
 void cheb_rec(syk_dtype dtype, int64_t n, void* out, const void* w, const void* y, const void* z, const void* x,

@@ -70,7 +70,7 @@ struct syk_terms_s {
     syk::HamiltonianDev H;
     syk::Workspace ws;
     unsigned upload_slot = 0;       // ring position of small coefficient uploads
-    std::map<int, std::unique_ptr<syk::DevBuf>> grad_chunks;   // per tile_bits
+    std::map<int, std::unique_ptr<syk::DevBuf>> grad_chunks;   // per (tile_bits, layouts)
     std::map<int, int> grad_nchunks, grad_nmembers;
     // H restricted to each fermion-parity sector, built on first use
     struct Sector {

@@ -121,3 +121,83 @@ def test_spectrum_bounds_inside_exact():
     lo, hi = api.spectrum_bounds(T, _gpu(inputs.typical_state(N, 1)), 60)
     assert ev[0] - 1e-9 <= lo <= ev[0] + 1e-6
     assert ev[-1] - 1e-6 <= hi <= ev[-1] + 1e-9
+
+
+def _overlap_sample(N, count):
+    """Sampled couplings plus fixed ones of every mask kind: both Majoranas of
+    two qubits (diagonal), of one qubit (two flipped qubits), and four distinct
+    qubits at the top and bottom of the register (masks that run in the rotated
+    and in the natural row layout)."""
+    qs = jw.quartets(N)
+    fixed = [(0, 1, 2, 3), (0, 1, N - 2, N - 1), (2, 3, 5, N - 3), (0, 4, N - 5, N - 2),
+             (N - 8, N - 6, N - 4, N - 1), (1, 3, 5, 7), (4, 9, 14, N - 1)]
+    idx = {q: n for n, q in enumerate(qs)} if N <= 20 else None
+    ks = [idx[q] if idx else qs.index(q) for q in fixed]
+    ks += [int(k) for k in inputs.quartet_sample(N, 7, count)]
+    return sorted(set(ks))
+
+
+@pytest.mark.parametrize("N,count", [(16, None), (36, 16), (44, 6)])
+def test_coupling_overlaps_vs_checker(N, count):
+    """sum_p w_p Re <g_p| dH/dJ_n |v_p> (the per-coupling reductions of the
+    gradient) against the checker's matrix-free quartets: every coupling at
+    N=16; sampled and fixed couplings at N=36 (two row layouts) and N=44
+    (dim 2^22, the gradient workload's size).  Three pairs: an odd count."""
+    ws = (0.5, -2.0, 1.25) if N < 44 else (0.5, -2.0)
+    host = [(inputs.typical_state(N, 10 + p), inputs.typical_state(N, 20 + p), w) for p, w in enumerate(ws)]
+    T = api.Terms(N, inputs.couplings(N, 0))
+    got = api.coupling_overlaps(T, [(_gpu(g), _gpu(v), w) for g, v, w in host])
+    qs = jw.quartets(N)
+    ks = list(range(len(qs))) if count is None else _overlap_sample(N, count)
+    want = jw.coupling_overlaps(N, [qs[k] for k in ks], host)
+    scale = max(1e-3, np.abs(want).max())
+    assert np.abs(got[ks] - want).max() <= 1e-11 * scale
+    T.close()
+
+
+def test_grad_vs_finite_differences_n36():
+    """Sampled couplings at N=36 (masks in both row layouts) against central
+    differences of the GPU forward."""
+    N = 36
+    J = inputs.couplings(N, 0)
+    psi = _gpu(inputs.typical_state(N, 1))
+    T = api.Terms(N, J)
+    lo, hi = api.spectrum_bounds(T, psi, 60)
+    e_h = 1.2 * max(abs(lo), abs(hi))
+    o = api.cheb_opts(degree=16, dt=0.1, tau_steps=1, checkpoint_every=4, e_halfwidth=e_h)
+    F, g = api.grad_couplings(T, 0, 1, 1.0, 0.2, psi, o)
+    ks = _overlap_sample(N, 4)
+    h = 1e-5
+    for k in ks:
+        vals = []
+        for s in (1.0, -1.0):
+            Jp = J.copy()
+            Jp[k] += s * h
+            Tp = api.Terms(N, Jp)
+            vals.append(api.cheb_otoc(Tp, 0, 1, 1.0, 0.2, psi, o))
+            Tp.close()
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * np.abs(g).max() + 1e-9
+    T.close()
+
+
+def test_grad_euler_identity_n44():
+    """The gradient workload's size (N=44, dim 2^22, 135,751 couplings, masks in
+    two row layouts) on a short schedule: sum_k J_k dF/dJ_k = beta dF/dbeta +
+    t dF/dt, an exact property of F (H is linear in J) that checks every
+    coupling's derivative at once."""
+    N = 44
+    J = inputs.couplings(N, 0)
+    psi = _gpu(inputs.typical_state(N, 1))
+    T = api.Terms(N, J)
+    lo, hi = api.spectrum_bounds(T, psi, 60)
+    e_h = 1.2 * max(abs(lo), abs(hi))
+    beta, t, n = 5.0, 0.2, 2
+    opts = lambda tt: api.cheb_opts(degree=32, dt=tt / n, tau_steps=1, checkpoint_every=10, e_halfwidth=e_h)
+    F, g = api.grad_couplings(T, 0, 1, beta, t, psi, opts(t))
+    d = 1e-4
+    Fb = [api.cheb_otoc(T, 0, 1, beta + s * d, t, psi, opts(t)) for s in (1, -1)]
+    Ft = [api.cheb_otoc(T, 0, 1, beta, t + s * d, psi, opts(t + s * d)) for s in (1, -1)]
+    rhs = beta * (Fb[0] - Fb[1]) / (2 * d) + t * (Ft[0] - Ft[1]) / (2 * d)
+    assert abs(np.dot(J, g) - rhs) <= 1e-7
+    T.close()

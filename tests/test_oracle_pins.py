@@ -455,3 +455,33 @@ def test_sector_rows_split_h_and_majoranas(N):
     assert np.abs(ev - evs).max() < 1e-12
     for chi in jw.dense_majoranas(N):
         assert np.abs(chi[np.ix_(r0, r0)]).max() == 0.0 and np.abs(chi[np.ix_(r1, r1)]).max() == 0.0
+
+
+@pytest.mark.parametrize("N", [8, 10])
+def test_coupling_overlaps_pins(N):
+    """Matrix-free quartet operators against the np.kron construction, their
+    algebra (Hermitian, square = 1/16 from four anticommuting Majoranas of square
+    1/2), and linearity: sum_n J_n overlap_n = sum_p w_p Re <g_p|H|v_p>."""
+    chis = jw.dense_majoranas(N)
+    qs = jw.quartets(N)
+    rng = np.random.default_rng(11)
+    D = 1 << (N // 2)
+    vec = lambda: rng.normal(size=D) + 1j * rng.normal(size=D)
+    v = vec()
+    for n in range(0, len(qs), 7):
+        Q = jw.dense_quartet(N, n, chis)
+        assert np.abs(jw.quartet_apply(N, qs[n], v) - Q @ v).max() <= 1e-14
+        assert np.abs(Q - Q.conj().T).max() <= 1e-15
+        assert np.abs(Q @ Q - np.eye(D) / 16).max() <= 1e-15
+    J = inputs.couplings(N, 4)
+    H = jw.dense_H(N, J, chis)
+    pairs = [(vec(), vec(), 0.7), (vec(), vec(), -1.3)]
+    ov = jw.coupling_overlaps(N, qs, pairs)
+    direct = sum(w * np.vdot(g, H @ x).real for g, x, w in pairs)
+    assert abs(np.dot(J, ov) - direct) <= 1e-10 * max(1.0, abs(direct))
+    # a single coupling switched on: the overlap is the whole product
+    k = len(qs) // 3
+    Jk = np.zeros_like(J)
+    Jk[k] = 1.0
+    Hk = jw.dense_H(N, Jk, chis)
+    assert abs(ov[k] - sum(w * np.vdot(g, Hk @ x).real for g, x, w in pairs)) <= 1e-12
