@@ -172,7 +172,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-N", type=int, default=40, help="size of the batched leg (0: skip)")
-    ap.add_argument("--grad-N", type=int, default=36, help="size of the gradient leg (0: skip)")
+    ap.add_argument("--grad-N", type=int, default=44, help="size of the gradient leg (0: skip)")
+    ap.add_argument("--grad-t", type=float, default=0.5,
+                    help="t* of the gradient leg (a multiple of dt = 0.1; the cost ratio barely depends on it)")
     ap.add_argument("--profile-apply", type=int, default=0,
                     help="only run this many complex128 apply_H calls and one 1 GiB device copy "
                          "(for hardware-counter runs), then exit")
@@ -278,7 +280,7 @@ def main():
     if args.grad_N > 0:
         torch.cuda.empty_cache()
         log(f"[bench] gradient leg: N={args.grad_N}")
-        grad = grad_leg(api, inputs, torch, dev, args.grad_N, 1.0, 32, 0.1, 5.0)
+        grad = grad_leg(api, inputs, torch, dev, args.grad_N, args.grad_t, 32, 0.1, 5.0)
         log(f"[bench] grad/fwd = {grad['grad_fwd_ratio']:.2f}")
 
     traffic = traffic_from_profile(f"N{N}_c128")

@@ -196,13 +196,15 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
         __syncthreads();
 
         uint32_t mi = C.first;
+        QRec qn = rec[mi];   // the next QUAD record, loaded one mask ahead (records run one past the end)
         auto class_loop = [&](auto cls) {
             constexpr int CL = decltype(cls)::value;
             constexpr uint32_t XK = (uint32_t)class_bits(CL, KB, 1);   // k bits the masks flip
             constexpr uint32_t ZK = (uint32_t)class_bits(CL, KB, 2);   // k bits in their Z string
             const uint32_t n = (C.cnt[CL >> 2] >> (8 * (CL & 3))) & 0xffu;
             for (uint32_t i = 0; i < n; ++i, ++mi) {
-                const QRec q = rec[mi];
+                const QRec q = qn;
+                qn = rec[mi + 1];
                 const uint32_t ia = __builtin_amdgcn_udot4(__builtin_amdgcn_perm(B1, B0, q.sel), kDotW,
                                                            (mi - C.first) * 16u * esz, false);
                 const uint32_t sl = (uint32_t)__popc(tid & q.zl) << 31;

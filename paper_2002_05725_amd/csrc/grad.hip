@@ -11,8 +11,8 @@
 // buffer; k_bins_reduce adds the slices in a fixed order.
 //
 // QUAD bins depend on the row only through its bits at the four flipped
-// qubits: the lanes of a wave that agree on those bits are summed with a
-// butterfly of lane exchanges first, and one lane per bin adds to LDS.  PAIR
+// qubits: the lanes of a wave that agree on those bits are summed with DPP
+// row shifts and permlane swaps first, and one lane per bin adds to LDS.  PAIR
 // and DIAG bins are linear in sum_p w_p conj(g_p[r]) v_p[r ^ x], which each
 // thread sums over the pairs in registers and bins once per tile.
 #include "grad.hpp"
@@ -38,32 +38,60 @@ __device__ __forceinline__ uint32_t quad_index(uint32_t r, uint32_t qpack)
            (bit(r, mask_q(qpack, 3)) << 3);
 }
 
-// v from the lane whose index differs from this lane's in bit B (B < 6).
+// v plus the value of the partner lane that differs from this lane in in-wave
+// lane bit B.  Bits 0..3: a DPP row shift by 2^B, whose partner is this lane
+// minus 2^B, so only lanes with bit B set receive the pair's sum.  Bits 4 and
+// 5: the gfx950 permlane swaps (rows 2j <-> 2j+1 of 16 lanes; halves of 32
+// lanes), which give every lane the sum.  All VALU: no LDS round trip.
 template <int B>
-__device__ __forceinline__ double lane_xor(double v)
+__device__ __forceinline__ double add_partner(double v)
 {
-    if constexpr (B < 5) {
-        // ds_swizzle bit mode: and_mask 0x1f, or_mask 0, xor_mask 1 << B
-        constexpr int pat = 0x1f | ((1 << B) << 10);
-        const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), pat);
-        const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), pat);
-        return __hiloint2double(hi, lo);
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    if constexpr (B < 4) {
+        constexpr int ctrl = 0x110 + (1 << B);   // row_shr:2^B
+        const int plo = __builtin_amdgcn_mov_dpp(lo, ctrl, 0xf, 0xf, true);
+        const int phi = __builtin_amdgcn_mov_dpp(hi, ctrl, 0xf, 0xf, true);
+        return v + __hiloint2double(phi, plo);
+    } else if constexpr (B == 4) {
+        const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
     } else {
-        return __shfl_xor(v, 32);
+        const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
     }
 }
 
-// Sum of v over the lanes of this wave that agree with this lane on every
-// in-wave lane bit set in keep (bits 0..5 of the lane index).
-__device__ __forceinline__ double group_sum(double v, uint32_t keep)
+// Sums of a and of b over the lanes of this wave that agree with this lane on
+// every in-wave lane bit set in keep (bits 0..5 of the lane index), complete
+// in the lane group_rep picks out of each group.  keep must be wave-uniform,
+// every lane of the workgroup must call it, and keep must include every lane
+// bit at or above the workgroup's own lane bits (the exchanges would read the
+// registers of lanes that do not run).
+template <int B>
+__device__ __forceinline__ void group_stage(double& a, double& b, uint32_t keep)
 {
-    if (!(keep & 1u)) v += lane_xor<0>(v);
-    if (!(keep & 2u)) v += lane_xor<1>(v);
-    if (!(keep & 4u)) v += lane_xor<2>(v);
-    if (!(keep & 8u)) v += lane_xor<3>(v);
-    if (!(keep & 16u)) v += lane_xor<4>(v);
-    if (!(keep & 32u)) v += lane_xor<5>(v);
-    return v;
+    if (!(keep & (1u << B))) {
+        a = add_partner<B>(a);
+        b = add_partner<B>(b);
+    }
+}
+__device__ __forceinline__ void group_sum(double& a, double& b, uint32_t keep)
+{
+    group_stage<0>(a, b, keep);
+    group_stage<1>(a, b, keep);
+    group_stage<2>(a, b, keep);
+    group_stage<3>(a, b, keep);
+    group_stage<4>(a, b, keep);
+    group_stage<5>(a, b, keep);
+}
+
+// The lane of a group_sum group that holds the sum: its bits 0..3 outside keep
+// are set, its bits 4 and 5 outside keep clear.
+__device__ __forceinline__ bool group_rep(uint32_t lane, uint32_t keep)
+{
+    return ((lane | keep) & 15u) == 15u && (lane & ~keep & 48u) == 0u;
 }
 
 // out = b (w - gamma y) + s z + c x ; acc += ca out (acc optional).  Null
@@ -134,6 +162,7 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const uint32_t nt = blockDim.x;
     const uint32_t lb = 31u - __clz(nt);                              // lane bits (8 when RPT > 1)
+    const uint32_t absent = 63u & ~(nt - 1u);                          // in-wave lane bits no thread has
     const uint32_t tile_elems = nt * RPT;
     constexpr int PP = kGradPairsPerStage;
     c128* src = reinterpret_cast<c128*>(smem_raw);                  // [PP][tile_elems]
@@ -226,9 +255,10 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
                             ai += pi;
                         }
                         const uint32_t s = parity(base & m.zbase);
-                        ar = group_sum(flip(ar, s), 0u);
-                        ai = group_sum(flip(ai, s), 0u);
-                        if ((tid & 63u) == 0u) {
+                        ar = flip(ar, s);
+                        ai = flip(ai, s);
+                        group_sum(ar, ai, absent);
+                        if (group_rep(tid & 63u, absent)) {
                             double* mb = bins + 2 * local[j];
                             const uint32_t idx = quad_index(base, m.qpack);
                             atomicAdd(&mb[2 * idx], ar);
@@ -250,30 +280,34 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
                             const uint32_t il = __builtin_amdgcn_udot4(__builtin_amdgcn_perm(B1, B0, q.sel), 0x08040201u,
                                                                        fo & 15u, false);
                             const uint32_t sl = ((uint32_t)__popc(tid & q.zl) ^ (fo >> 4)) << 31;
-                            const uint32_t keep = q.koffs >> 24;
+                            const uint32_t keep = (q.koffs >> 24) | absent;
                             double er[RPT], ei[RPT];   // by the flipped k bits p = k & XK
 #pragma unroll
                             for (int pp = 0; pp < RPT; ++pp) er[pp] = ei[pp] = 0.0;
                             const uint32_t sb = tid ^ q.xoff;
 #pragma unroll
                             for (int k = 0; k < RPT; ++k) {
-                                double pr = 0.0, pi = 0.0;
+                                // += (sign of row k) conj(w g) x, straight into the entry's sums
+                                const bool neg = (__builtin_popcount((uint32_t)k & ZK) & 1) != 0;
+                                double& a = er[k & (int)XK];
+                                double& b = ei[k & (int)XK];
 #pragma unroll
                                 for (int u = 0; u < PP; ++u) {
                                     const c128 x = src[u * tile_elems + sb + (((uint32_t)k ^ XK) << lb)];
-                                    pr += gk[u][k].re * x.re + gk[u][k].im * x.im;
-                                    pi += gk[u][k].re * x.im - gk[u][k].im * x.re;
+                                    const double gr = neg ? -gk[u][k].re : gk[u][k].re;
+                                    const double gi = neg ? -gk[u][k].im : gk[u][k].im;
+                                    a = fma(gr, x.re, a);
+                                    a = fma(gi, x.im, a);
+                                    b = fma(gr, x.im, b);
+                                    b = fma(-gi, x.re, b);
                                 }
-                                const bool neg = (__builtin_popcount((uint32_t)k & ZK) & 1) != 0;
-                                er[k & (int)XK] += neg ? -pr : pr;
-                                ei[k & (int)XK] += neg ? -pi : pi;
                             }
-                            const bool rep = ((tid & 63u) & ~keep) == 0u;   // one lane per bin and wave
+                            const bool rep = group_rep(tid & 63u, keep);   // one lane per bin and wave
 #pragma unroll
                             for (int pp = 0; pp < RPT; ++pp) {
                                 if ((pp & ~(int)XK) != 0) continue;
-                                const double ar = group_sum(flip31(er[pp], sl), keep);
-                                const double ai = group_sum(flip31(ei[pp], sl), keep);
+                                double ar = flip31(er[pp], sl), ai = flip31(ei[pp], sl);
+                                group_sum(ar, ai, keep);
                                 uint32_t idx = il;
 #pragma unroll
                                 for (int b = 0; b < KB; ++b)
