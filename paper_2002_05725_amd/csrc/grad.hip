@@ -160,14 +160,16 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
 {
     constexpr int KB = ilog2c(RPT);
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const uint32_t nt = blockDim.x;
-    const uint32_t lb = 31u - __clz(nt);                              // lane bits (8 when RPT > 1)
+    // threads and lane bits: 256 and 8 whenever a thread owns several rows
+    // (compile-time, so that row offsets become immediate LDS offsets)
+    const uint32_t nt = RPT > 1 ? 256u : blockDim.x;
+    const uint32_t lb = RPT > 1 ? 8u : 31u - __clz(nt);
     const uint32_t absent = 63u & ~(nt - 1u);                          // in-wave lane bits no thread has
     const uint32_t tile_elems = nt * RPT;
     constexpr int PP = kGradPairsPerStage;
     c128* src = reinterpret_cast<c128*>(smem_raw);                  // [PP][tile_elems]
     double* bins = reinterpret_cast<double*>(src + PP * tile_elems);   // [kGradBinCap][2]
-    uint32_t* fold = reinterpret_cast<uint32_t*>(bins + 2 * kGradBinCap);   // [kChunkMasks]
+    uint32_t* fold = reinterpret_cast<uint32_t*>(bins + 2 * kGradBinCap);   // [kChunkMasks + 1]
     const uint32_t tid = threadIdx.x;
     // bits 0..3 and 4..7 of tid, one per byte (table-index gather)
     uint32_t B0 = 0, B1 = 0;
@@ -268,15 +270,20 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
                 } else {
                     // near QUAD members, class by class
                     uint32_t j = C.first;
+                    // the next member's record and fold, loaded one member ahead (both lists run one past the end)
+                    GRec qn = grec[j];
+                    uint32_t fon = fold[0];
                     auto class_loop = [&](auto cls) {
                         constexpr int CL = decltype(cls)::value;
                         constexpr uint32_t XK = (uint32_t)class_bits(CL, KB, 1);   // k bits the masks flip
                         constexpr uint32_t ZK = (uint32_t)class_bits(CL, KB, 2);   // k bits in their Z string
                         const uint32_t n = (C.cnt[CL >> 2] >> (8 * (CL & 3))) & 0xffu;
                         for (uint32_t i = 0; i < n; ++i, ++j) {
-                            const GRec q = grec[j];
+                            const GRec q = qn;
                             const uint32_t slot = j - C.first;
-                            const uint32_t fo = fold[slot];
+                            const uint32_t fo = fon;
+                            qn = grec[j + 1];
+                            fon = fold[slot + 1];
                             const uint32_t il = __builtin_amdgcn_udot4(__builtin_amdgcn_perm(B1, B0, q.sel), 0x08040201u,
                                                                        fo & 15u, false);
                             const uint32_t sl = ((uint32_t)__popc(tid & q.zl) ^ (fo >> 4)) << 31;
@@ -480,6 +487,7 @@ GradChunks make_grad_chunks(const std::vector<MaskRec>& masks, const std::vector
         }
         g.chunks.push_back(b.c);
     }
+    g.grec.push_back(GRec{});   // one record past the end: the kernel loads one member ahead
     return g;
 }
 
@@ -510,7 +518,7 @@ void grad_bins(syk_terms_s& h, const std::vector<const void*>& g, const std::vec
     // 1024-row tiles, 256 threads (the kernel's launch bound)
     const ApplyTuning tune{10, 256, 1};
     const ApplyPlan P = plan_apply(H.M, 1, SYK_C128, &tune);
-    require(P.nt <= 256, "gradient: launch shape");
+    require(P.nt <= 256 && (P.rpt == 1 || P.nt == 256), "gradient: launch shape");
     const bool two = P.two_layouts != 0;
     // mask records, chunk records, member list, LDS bin offsets and QUAD member
     // records in one device buffer
@@ -595,11 +603,11 @@ void grad_bins(syk_terms_s& h, const std::vector<const void*>& g, const std::vec
 
     double* partial = (double*)h.ws.get("grad_partial", (size_t)nblk * T.n_bins * 2 * sizeof(double));
     const size_t lds = (size_t)kGradPairsPerStage * ((size_t)1 << P.tile_bits) * sizeof(c128) +
-                       (size_t)kGradBinCap * 2 * sizeof(double) + (size_t)kChunkMasks * sizeof(uint32_t);
+                       (size_t)kGradBinCap * 2 * sizeof(double) + (size_t)(kChunkMasks + 1) * sizeof(uint32_t);
     const KRec* krec = it->second->as<KRec>();
     const GChunk* chunks = reinterpret_cast<const GChunk*>(krec + T.masks.size());
     const GRec* grec = reinterpret_cast<const GRec*>(chunks + L.n_chunks);
-    const uint32_t* members = reinterpret_cast<const uint32_t*>(grec + h.grad_nmembers[key]);
+    const uint32_t* members = reinterpret_cast<const uint32_t*>(grec + h.grad_nmembers[key] + 1);
     const uint32_t* local = members + h.grad_nmembers[key];
     const dim3 grid(nblk * L.chunk_groups), block(P.nt);
     switch (P.rpt) {

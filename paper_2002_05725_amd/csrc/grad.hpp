@@ -40,7 +40,7 @@ struct GradChunks {
     std::vector<GChunk> chunks;
     std::vector<uint32_t> members;   // mask index of each member
     std::vector<uint32_t> local;     // first LDS bin of each member
-    std::vector<GRec> grec;          // per member (zero for all but near QUAD members)
+    std::vector<GRec> grec;          // per member (zero for all but near QUAD members), plus one zero record
 };
 
 // masks: every mask in mask order, in the coordinates of its layout
