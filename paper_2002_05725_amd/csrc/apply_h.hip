@@ -163,6 +163,9 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
 
     for (int g = 0; g < L.n_chunks; ++g) {
         const QApplyChunk C = chunks[g];
+        uint32_t n_flat = 0;   // flat PAIR masks (no flipped k bit), first among the PAIR records
+#pragma unroll
+        for (int b = 0; b < 8; ++b) n_flat += (C.pcnt[b >> 2] >> (8 * (b & 3))) & 0xffu;
         __syncthreads();   // previous chunk is done with src / tabs
         if (C.new_tile) {
             const uint64_t sbase = (uint64_t)(tile ^ C.x_high) << L.tile_bits;
@@ -181,17 +184,19 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
             S.tabs[e] = o;
         }
         // PAIR slots (after the QUAD tables): for each row k and term e, the part
-        // of L_e(r) that does not depend on the lane, W_e + sum over tile and k
-        // bits c of w_{e,c} r_c.  One slot holds RPT * 4 values.
+        // of L_e(r) that does not depend on the lane, t_{k,e} = W_e + sum over
+        // tile and k bits c of w_{e,c} r_c.  One slot holds RPT * 4 values (flat
+        // masks, below, only row 0).
         for (uint32_t v = tid; v < C.n_pair * (RPT * 4); v += nt) {
             const uint32_t p = v / (RPT * 4), k = (v >> 2) % RPT, e = v & 3u;
-            const uint32_t tab = rec[C.first + C.n_quad + p].tab;
-            const R* w = T.w2 + (((size_t)tab * T.n_real + rc) * 4 + e) * (M + 1);
+            if (p < n_flat && k != 0) continue;   // flat masks use row 0 only
+            const QRec& pq = rec[C.first + C.n_quad + p];
+            const R* w = T.w2 + (((size_t)pq.tab * T.n_real + rc) * 4 + e) * (M + 1);
             const uint32_t rb = base | (k << lb);
             R acc = w[M];
             for (int c = (int)lb; c < M; ++c)
                 if ((rb >> c) & 1u) acc += w[c];
-            reinterpret_cast<R*>(S.tabs)[(C.n_quad + p) * (16 * esz / sizeof(R)) + k * 4 + e] = acc;
+            reinterpret_cast<R*>(reinterpret_cast<char*>(S.tabs) + pq.sel)[k * 4 + e] = acc;
         }
         __syncthreads();
 
@@ -236,11 +241,11 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
         // PAIR: D = (-1)^{|r & zbase|} sum_e phi_e (-1)^{s_q0 e_0 + s_q1 e_1} L_e(r),
         // phi_e = Phi[idx = 3][e] (the entry with s_q0 = s_q1 = 0), L_e(r) =
         // W_e + sum_c w_{e,c} r_c: the lane bits here, the rest staged per row k.
-        for (uint32_t i = 0; i < C.n_pair; ++i, ++mi) {
-            const QRec q = rec[mi];
+        // The lane part of a thread's rows: l_e = sum over lane bits c of w_{e,c} tid_c.
+        auto lane_forms = [&](const QRec& q, R (&l)[4]) {
             const R* w = T.w2 + ((size_t)q.tab * T.n_real + rc) * 4 * (M + 1);
-            const cplx<R>* ph = T.phi2 + (size_t)q.tab * 16 + 12;
-            R l[4] = {R(0), R(0), R(0), R(0)};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) l[e] = R(0);
 #pragma unroll
             for (int c = 0; c < kLaneBits; ++c) {
                 if (c >= (int)lb) break;
@@ -248,11 +253,72 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
 #pragma unroll
                 for (int e = 0; e < 4; ++e) l[e] = fma(w[e * (M + 1) + c], b, l[e]);
             }
+        };
+        // Flat PAIR masks (no flipped k bit), by the k bits ZK of their Z string
+        // (compile-time row signs).  The qubit signs s_q0, s_q1 and the lane and
+        // tile parts of the Z-string sign are the same on all of a thread's rows,
+        // and L_e is linear in the k bits:
+        //   D_k = (-1)^{|k & ZK|} (A + sum over set bits b of k of Om_b),
+        //   A = (-1)^{s} sum_e phi_e sigma_e (l_e + t_{0,e}),
+        //   Om_b = (-1)^{s} sum_e phi_e sigma_e w_{e,lb+b},
+        // sigma_e = (-1)^{s_q0 e_0 + s_q1 e_1}: one complex add per row.
+        auto flat_loop = [&](auto cls) {
+            constexpr int ZK = decltype(cls)::value;
+            const uint32_t n = (C.pcnt[ZK >> 2] >> (8 * (ZK & 3))) & 0xffu;
+            for (uint32_t i = 0; i < n; ++i, ++mi) {
+                const QRec q = rec[mi];
+                const R* w = T.w2 + ((size_t)q.tab * T.n_real + rc) * 4 * (M + 1);
+                const cplx<R>* ph = T.phi2 + (size_t)q.tab * 16 + 12;
+                R l[4];
+                lane_forms(q, l);
+                const R* t0 = reinterpret_cast<const R*>(tab_b + q.sel);   // t_{0,e}
+                const uint32_t rl = tid | base;
+                const uint32_t sa = bit(rl, mask_q(q.qpack, 0)) ^ 1u, sbb = bit(rl, mask_q(q.qpack, 1)) ^ 1u;
+                const uint32_t s = parity(rl & q.zbase);
+                // sum_e phi_e sigma_e y_e, signed by s
+                auto combine = [&](R y0, R y1, R y2, R y3) {
+                    const R b1 = flip(y1, sa), b2 = flip(y2, sbb), b3 = flip(y3, sa ^ sbb);
+                    cplx<R> o;
+                    o.re = flip(ph[0].re * y0 + ph[1].re * b1 + ph[2].re * b2 + ph[3].re * b3, s);
+                    o.im = flip(ph[0].im * y0 + ph[1].im * b1 + ph[2].im * b2 + ph[3].im * b3, s);
+                    return o;
+                };
+                cplx<R> X[RPT];
+                X[0] = combine(l[0] + t0[0], l[1] + t0[1], l[2] + t0[2], l[3] + t0[3]);
+#pragma unroll
+                for (int b = 0; b < KB; ++b) {
+                    const int c = (int)lb + b;
+                    const cplx<R> om = combine(w[c], w[(M + 1) + c], w[2 * (M + 1) + c], w[3 * (M + 1) + c]);
+#pragma unroll
+                    for (int k = 1 << b; k < (2 << b); ++k) {
+                        X[k].re = X[k - (1 << b)].re + om.re;
+                        X[k].im = X[k - (1 << b)].im + om.im;
+                    }
+                }
+                const uint32_t sb = tid_b ^ q.xoff;
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) {
+                    const bool neg = (__builtin_popcount((uint32_t)k & (uint32_t)ZK) & 1) != 0;
+                    const cplx<R> v = src_at(sb + ((uint32_t)k << kLaneBits) * esz);
+                    cmac(pr[k], pi[k], neg ? -X[k].re : X[k].re, neg ? -X[k].im : X[k].im, v);
+                }
+            }
+        };
+        if (RPT > 1) {
+            for_each_class(flat_loop, std::make_integer_sequence<int, RPT>{});
+        } else {
+            flat_loop(std::integral_constant<int, 0>{});
+        }
+        for (uint32_t i = n_flat; i < C.n_pair; ++i, ++mi) {
+            const QRec q = rec[mi];
+            const cplx<R>* ph = T.phi2 + (size_t)q.tab * 16 + 12;
+            R l[4];
+            lane_forms(q, l);
             const uint32_t q0 = mask_q(q.qpack, 0), q1 = mask_q(q.qpack, 1);
             const uint32_t rl = tid | base;
             const uint32_t sa_l = bit(rl, q0) ^ 1u, sb_l = bit(rl, q1) ^ 1u, s_l = parity(rl & q.zbase);
             const uint32_t sb = tid_b ^ q.xoff;
-            const R* tk = reinterpret_cast<const R*>(tab_b + (C.n_quad + i) * 16u * esz);
+            const R* tk = reinterpret_cast<const R*>(tab_b + q.sel);
 #pragma unroll
             for (int k = 0; k < RPT; ++k) {
                 const uint32_t kr = (uint32_t)k << lb;
@@ -435,26 +501,39 @@ void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int la
     const uint32_t kbits_mask = (1u << kb) - 1u;
     auto quad_class_of = [&](const MaskRec& m) { return quad_class(m.x, m.zbase, lane_bits, kb); };
     auto type_of = [](const MaskRec& m) { return m.type_tab >> 28; };
+    // PAIR masks flipping no k bit, and the k-bit pattern of their Z string
+    auto is_k_bit = [&](uint32_t q) { return q >= (uint32_t)lane_bits && q < (uint32_t)tile_bits; };
+    auto flat_pair = [&](const MaskRec& m) {
+        return type_of(m) == MASK_PAIR && !is_k_bit(mask_q(m.qpack, 0)) && !is_k_bit(mask_q(m.qpack, 1));
+    };
+    auto zk_of = [&](const MaskRec& m) { return (int)((m.zbase >> lane_bits) & kbits_mask); };
+    // table slots (16 entries each) a mask stages
+    auto slots_of = [&](const MaskRec& m) { return type_of(m) == MASK_DIAG ? 0u : 1u; };
     size_t i = 0;
     uint32_t prev_high = 0xffffffffu;
     while (i < masks.size()) {
         // masks of one chunk: same x_high, at most apply_chunk_masks(esz)
         std::vector<uint32_t> mem;
         const uint32_t xh = masks[i].x >> tile_bits;
-        while (i < masks.size() && (masks[i].x >> tile_bits) == xh && mem.size() < (size_t)apply_chunk_masks(esz)) {
+        const uint32_t cap = (uint32_t)apply_chunk_masks(esz);   // masks and table slots per chunk
+        uint32_t used = 0;
+        while (i < masks.size() && (masks[i].x >> tile_bits) == xh && mem.size() < cap) {
             const MaskRec& m = masks[i];
             // far: coefficient constant over a tile (no flipped qubit and no Z-string bit inside it)
-            if (type_of(m) == MASK_QUAD && (m.x & row_mask) == 0u && (m.zbase & row_mask) == 0u)
+            if (type_of(m) == MASK_QUAD && (m.x & row_mask) == 0u && (m.zbase & row_mask) == 0u) {
                 far.push_back({m.x >> tile_bits, m.qpack, m.zbase, m.type_tab & 0x0fffffffu});
-            else
+            } else {
+                if (used + slots_of(m) > cap) break;
+                used += slots_of(m);
                 mem.push_back((uint32_t)i);
+            }
             ++i;
         }
         if (mem.empty()) continue;
         auto key = [&](uint32_t j) {
             const MaskRec& m = masks[j];
             const uint32_t t = type_of(m);
-            return t == MASK_QUAD ? quad_class_of(m) : t == MASK_PAIR ? 100 : 200;
+            return t == MASK_QUAD ? quad_class_of(m) : t == MASK_PAIR ? (flat_pair(m) ? 100 + zk_of(m) : 150) : 200;
         };
         std::stable_sort(mem.begin(), mem.end(), [&](uint32_t a, uint32_t b) { return key(a) < key(b); });
         QApplyChunk c{};
@@ -462,6 +541,7 @@ void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int la
         c.first = (uint32_t)recs.size();
         c.new_tile = (xh != prev_high) ? 1u : 0u;
         prev_high = xh;
+        uint32_t slot = 0;
         for (uint32_t j : mem) {
             const MaskRec& m = masks[j];
             const uint32_t t = type_of(m);
@@ -483,11 +563,19 @@ void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int la
                     if (b >= 0 && b < kb) r.koffs |= ((1u << q) * esz) << (8 * b);
                 }
             } else {
-                r.sel = 0x0c0c0c0cu;
+                r.sel = slot * 16u * esz;
                 r.koffs = (m.x >> lane_bits) & kbits_mask;
-                if (t == MASK_PAIR) ++c.n_pair;
-                else ++c.n_diag;
+                if (t == MASK_PAIR) {
+                    ++c.n_pair;
+                    if (flat_pair(m)) {
+                        const int zk = zk_of(m);
+                        c.pcnt[zk >> 2] += 1u << (8 * (zk & 3));
+                    }
+                } else {
+                    ++c.n_diag;
+                }
             }
+            slot += slots_of(m);
             recs.push_back(r);
         }
         chunks.push_back(c);

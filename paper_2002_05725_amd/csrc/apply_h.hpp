@@ -30,7 +30,8 @@ enum : uint32_t {
 // what the QUAD loops read per mask; the rest serves table staging and the
 // PAIR / DIAG paths.
 struct alignas(16) QRec {
-    uint32_t sel;    // QUAD: byte selector gathering the lane bits of tid at q0..q3 (0x0c: not a lane bit)
+    uint32_t sel;    // QUAD: byte selector gathering the lane bits of tid at q0..q3 (0x0c: not a lane bit);
+                     // PAIR: byte offset of the mask's staged values in the chunk's table area
     uint32_t zl;     // lane bits of zbase
     uint32_t xoff;   // (x & lane mask) * element size: lane part of the source offset
     uint32_t koffs;  // QUAD: byte b = table byte offset of the index bit that k-bit b sets (0 if b is not flipped);
@@ -46,13 +47,15 @@ constexpr int kMaxKBits = 3;   // up to 8 rows per thread
 constexpr int kQuadClasses = 27;   // 3^kMaxKBits (k-bit flipped / in the Z string / neither)
 
 // One chunk of the apply kernel: masks sharing a source tile, QUAD masks first,
-// sorted by class, then PAIR, then DIAG.
+// sorted by class, then PAIR (those that flip no k bit first, sorted by the k
+// bits of their Z string), then DIAG.
 struct alignas(16) QApplyChunk {
     uint32_t x_high;    // source tile = tile ^ x_high
     uint32_t first;     // first record (index into the QRec array)
     uint32_t new_tile;  // x_high differs from the previous chunk's
     uint32_t n_quad;
-    uint32_t n_pair, n_diag, pad[2];
+    uint32_t n_pair, n_diag;
+    uint32_t pcnt[2];   // PAIR masks that flip no k bit, per k-bit pattern of zbase, one byte per pattern
     uint32_t cnt[8];    // QUAD masks per class, one byte per class
 };
 static_assert(sizeof(QApplyChunk) == 64, "QApplyChunk layout");
