@@ -1,0 +1,43 @@
+"""Host logic of the apply_H autotuner: candidate shapes, cache keys, the
+cache file round trip and the choice of the fastest candidate (no GPU)."""
+import json
+
+import pytest
+import torch
+
+from paper_2002_05725_amd import autotune
+
+
+def test_candidates_cover_valid_tiles():
+    assert autotune.candidates(52) == [(tb, x) for tb in (8, 9, 10, 11) for x in (1, 0)]
+    assert autotune.candidates(18) == [(8, 1), (8, 0), (9, 1), (9, 0)]
+    assert autotune.candidates(8) == [(4, 1), (4, 0)]
+    for N in (8, 12, 18, 24, 52, 60):
+        for tb, x in autotune.candidates(N):
+            assert tb <= N // 2 and tb <= 11 and x in (0, 1)
+
+
+def test_cache_key_separates_every_field():
+    keys = {autotune.cache_key(a, N, d, b) for a in ("gfx950", "gfx942") for N in (36, 40)
+            for d in (torch.complex64, torch.complex128) for b in (1, 64)}
+    assert len(keys) == 16
+    with pytest.raises(KeyError):
+        autotune.cache_key("gfx950", 36, torch.float32, 1)
+
+
+def test_cache_round_trip(tmp_path):
+    p = str(tmp_path / "sub" / "tune.json")
+    assert autotune.read_cache(p) == {}
+    autotune.write_cache(p, "k1", {"tile_bits": 11, "xcd_remap": 1, "ms": 2.0})
+    autotune.write_cache(p, "k2", {"tile_bits": 9, "xcd_remap": 0, "ms": 1.0})
+    autotune.write_cache(p, "k1", {"tile_bits": 10, "xcd_remap": 0, "ms": 1.5})
+    d = json.load(open(p))
+    assert d == {"k1": {"tile_bits": 10, "xcd_remap": 0, "ms": 1.5}, "k2": {"tile_bits": 9, "xcd_remap": 0, "ms": 1.0}}
+
+
+def test_pick_fastest_first_on_ties():
+    t = [{"tile_bits": 8, "xcd_remap": 1, "ms": 3.0}, {"tile_bits": 9, "xcd_remap": 1, "ms": 2.0},
+         {"tile_bits": 10, "xcd_remap": 0, "ms": 2.0}]
+    assert autotune.pick(t)["tile_bits"] == 9
+    with pytest.raises(ValueError):
+        autotune.pick([])
