@@ -30,9 +30,8 @@ struct KTerms {
     const uint32_t* __restrict__ qinfo;
     const cplx<R>* __restrict__ phi2;
     const R* __restrict__ w2;
-    const uint32_t* __restrict__ dz;
-    const R* __restrict__ dw;
-    int n_diag, n_real, M;
+    const double* __restrict__ diag;   // [n_real][dim]: the diagonal of H
+    int n_real, M;
 };
 
 struct KLayout {
@@ -334,17 +333,15 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
                 cmac(pr[k], pi[k], dre, dim, v);
             }
         }
-        // DIAG (source = own row)
+        // DIAG (source = own row): the precomputed diagonal of H
         for (uint32_t i = 0; i < C.n_diag; ++i, ++mi) {
-            const R* d = T.dw + (size_t)rc * T.n_diag;
+            const double* dg = T.diag + (uint64_t)rc * L.dim + base + tid;
 #pragma unroll
             for (int k = 0; k < RPT; ++k) {
-                const uint32_t r = base | (tid + ((uint32_t)k << lb));
+                const R d = (R)dg[(uint32_t)k << lb];
                 const cplx<R> v = src_at(tid_b + ((uint32_t)k << lb) * esz);
-                R s = R(0);
-                for (int n = 0; n < T.n_diag; ++n) s += flip(d[n], parity(r & T.dz[n]));
-                pr[k] = fma(s, v.re, pr[k]);
-                pi[k] = fma(s, v.im, pi[k]);
+                pr[k] = fma(d, v.re, pr[k]);
+                pi[k] = fma(d, v.im, pi[k]);
             }
         }
         if (kSplit) {
@@ -445,6 +442,32 @@ __global__ void __launch_bounds__(256) k_transpose(const cplx<R>* __restrict__ s
         }
         dst[o] = v;
     }
+}
+
+// diag[c][r] = sum_n dw[c][n] (-1)^{|r & dz_n|} for realisation c = blockIdx.y:
+// the diagonal of H (the masks with x = 0), FP64.
+__global__ void __launch_bounds__(256) k_diag_fill(const uint32_t* __restrict__ dz, const double* __restrict__ dw,
+                                                   int n_diag, uint64_t dim, double* __restrict__ diag)
+{
+    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= dim) return;
+    const double* d = dw + (size_t)blockIdx.y * n_diag;
+    double s = 0.0;
+    for (int n = 0; n < n_diag; ++n) s += (__popc((uint32_t)r & dz[n]) & 1u) ? -d[n] : d[n];
+    diag[(uint64_t)blockIdx.y * dim + r] = s;
+}
+
+// Fills H.diag the first time it is needed (on the stream, then waits for it).
+void ensure_diag(const HamiltonianDev& H, hipStream_t s)
+{
+    if (H.diag_ready) return;
+    const uint64_t dim = (uint64_t)1 << H.M;
+    H.diag.ensure((size_t)H.n_real * dim * sizeof(double));
+    const dim3 grid((uint32_t)((dim + 255) / 256), (uint32_t)H.n_real);
+    hipLaunchKernelGGL(k_diag_fill, grid, dim3(256), 0, s, H.dz, H.dw_d, H.n_diag, dim, H.diag.as<double>());
+    SYK_HIP(hipGetLastError());
+    SYK_HIP(hipStreamSynchronize(s));   // once per handle: later calls may come on other streams
+    H.diag_ready = true;
 }
 
 }  // namespace
@@ -762,6 +785,7 @@ void launch_apply_h(const HamiltonianDev& H, syk_dtype dtype, int nvec, const in
         H.rot_in.ensure(bytes);
         H.rot_out.ensure(bytes);
     }
+    ensure_diag(H, s);
     timing_begin(s);
     for (int sl = 0; sl < P.slices; ++sl) {
         KLayout L{};
@@ -783,10 +807,10 @@ void launch_apply_h(const HamiltonianDev& H, syk_dtype dtype, int nvec, const in
             const auto* ch = Tb.chunks.as<QApplyChunk>();
             const auto* rc = Tb.recs.as<QRec>();
             if (dtype == SYK_C128) {
-                KTerms<double> T{H.tab4_d, H.qinfo, H.phi2_d, H.w2_d, H.dz, H.dw_d, H.n_diag, H.n_real, M};
+                KTerms<double> T{H.tab4_d, H.qinfo, H.phi2_d, H.w2_d, H.diag.as<double>(), H.n_real, M};
                 launch_t<double>(P, T, ch, rc, L, ncols, src, dst, s);
             } else {
-                KTerms<float> T{H.tab4_f, H.qinfo, H.phi2_f, H.w2_f, H.dz, H.dw_f, H.n_diag, H.n_real, M};
+                KTerms<float> T{H.tab4_f, H.qinfo, H.phi2_f, H.w2_f, H.diag.as<double>(), H.n_real, M};
                 launch_t<float>(P, T, ch, rc, L, ncols, src, dst, s);
             }
         };

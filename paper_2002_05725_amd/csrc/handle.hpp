@@ -46,6 +46,10 @@ struct HamiltonianDev {
     mutable std::map<int, std::unique_ptr<ApplyTables>> apply_tables;
     // Rotated copies of psi and of the second layout's output (two-layout plans).
     mutable DevBuf rot_in, rot_out;
+    // The diagonal of H per realisation (FP64, [n_real][2^M]), filled on the
+    // first apply: it does not depend on the state.
+    mutable DevBuf diag;
+    mutable bool diag_ready = false;
 };
 
 // Named device workspaces, grown on demand and kept until the handle dies.
