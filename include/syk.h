@@ -278,6 +278,12 @@ typedef struct {
     int checkpoint_every;
     double e_center;
     double e_halfwidth;
+    int keep_segment;   /* 1: during the reverse sweep, keep the Chebyshev vectors
+                           of every step of a checkpoint segment from its
+                           recomputation when (checkpoint_every x (degree + 1))
+                           state vectors fit in half of the free device memory
+                           (held by the handle afterwards); 0: recompute each
+                           step's vectors again.  Results are identical. */
 } syk_cheb_opts;
 
 /*

@@ -25,7 +25,7 @@ class KrylovOpts(ctypes.Structure):
 class ChebOpts(ctypes.Structure):
     _fields_ = [("degree", ctypes.c_int), ("dt", ctypes.c_double), ("tau_steps", ctypes.c_int),
                 ("checkpoint_every", ctypes.c_int), ("e_center", ctypes.c_double),
-                ("e_halfwidth", ctypes.c_double)]
+                ("e_halfwidth", ctypes.c_double), ("keep_segment", ctypes.c_int)]
 
 
 class SykError(RuntimeError):

@@ -295,9 +295,10 @@ def lowest_eigenvalues(terms: Terms, psi0: torch.Tensor, k: int = 20, m: int = 2
 
 
 def cheb_opts(degree: int = 32, dt: float = 0.1, tau_steps: int = 1, checkpoint_every: int = 10,
-              e_center: float = 0.0, e_halfwidth: float = 1.0) -> ChebOpts:
+              e_center: float = 0.0, e_halfwidth: float = 1.0, keep_segment: bool = True) -> ChebOpts:
+    """Options of the Chebyshev forward and its reverse sweep (syk_cheb_opts)."""
     return ChebOpts(int(degree), float(dt), int(tau_steps), int(checkpoint_every), float(e_center),
-                    float(e_halfwidth))
+                    float(e_halfwidth), 1 if keep_segment else 0)
 
 
 def cheb_otoc(terms: Terms, i: int, j: int, beta: float, t_star: float, psi0: torch.Tensor, opts: ChebOpts) -> float:

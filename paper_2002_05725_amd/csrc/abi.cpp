@@ -99,54 +99,6 @@ std::vector<float> to_f32(const std::vector<double>& v) { return std::vector<flo
 
 namespace syk {
 
-const Group* HamiltonianDev::groups_for(int tile_bits, bool split_far) const
-{
-    const int key = tile_bits * 2 + (split_far ? 1 : 0);
-    auto it = groups.find(key);
-    if (it == groups.end()) {
-        std::vector<uint32_t> far;
-        std::vector<Group> g = make_groups(*host_masks, tile_bits, split_far ? &far : nullptr);
-        std::unique_ptr<DevBuf> b(new DevBuf());
-        upload(*b, g);
-        n_groups[key] = (int)g.size();
-        it = groups.emplace(key, std::move(b)).first;
-        if (split_far) {
-            std::vector<FarRec> fr;
-            for (uint32_t i : far) {
-                const MaskRec& m = (*host_masks)[i];
-                fr.push_back({m.x >> tile_bits, m.qpack, m.zbase, m.type_tab & 0x0fffffffu});
-            }
-            std::unique_ptr<DevBuf> fb(new DevBuf());
-            upload(*fb, fr);
-            n_fars[tile_bits] = (int)fr.size();
-            fars[tile_bits] = std::move(fb);
-        }
-    }
-    return it->second->as<Group>();
-}
-
-int HamiltonianDev::n_groups_for(int tile_bits, bool split_far) const
-{
-    groups_for(tile_bits, split_far);
-    return n_groups.at(tile_bits * 2 + (split_far ? 1 : 0));
-}
-
-const FarRec* HamiltonianDev::far_for(int tile_bits) const
-{
-    groups_for(tile_bits, true);
-    return fars.at(tile_bits)->as<FarRec>();
-}
-
-int HamiltonianDev::n_far_for(int tile_bits) const
-{
-    groups_for(tile_bits, true);
-    return n_fars.at(tile_bits);
-}
-
-}  // namespace syk
-
-namespace syk {
-
 // Device copies of a table set and the kernels' view of them.
 void make_device(const TermTables& T, DeviceTerms& d, HamiltonianDev& H)
 {
@@ -587,7 +539,9 @@ static ChebSettings check_cheb(syk_terms t, int i, int j, double beta, double t_
     require(i >= 0 && i < t->H.N && j >= 0 && j < t->H.N && i != j, "need 0 <= i, j < N with i != j");
     require(std::isfinite(beta) && beta >= 0, "beta must be finite and >= 0");
     require(std::isfinite(t_star) && t_star >= 0, "t_star must be finite and >= 0");
-    ChebSettings s{o->degree, o->dt, o->tau_steps, o->checkpoint_every, o->e_center, o->e_halfwidth};
+    require(o->keep_segment == 0 || o->keep_segment == 1, "keep_segment must be 0 or 1");
+    ChebSettings s{o->degree, o->dt, o->tau_steps, o->checkpoint_every, o->e_center, o->e_halfwidth,
+                   o->keep_segment};
     return s;
 }
 

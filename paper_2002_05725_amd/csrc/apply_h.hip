@@ -406,13 +406,6 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
     }
 }
 
-inline int ilog2(int64_t v)
-{
-    int l = 0;
-    while ((int64_t(1) << (l + 1)) <= v) ++l;
-    return l;
-}
-
 // dst = transpose of src viewed as a [2^log_h] x [2^log_w] matrix (row-major),
 // column by column of a block: dst[c][lo << log_h | hi] (+)= src[c][hi << log_w | lo].
 // 32 x 32 tiles through LDS so that both sides are read and written along
@@ -658,55 +651,23 @@ std::vector<MaskRec> layout_masks(const std::vector<MaskRec>& masks, int M, int 
 
 }  // namespace
 
-// Mask records for launch shape (tile_bits, nt), in mask order.
-std::vector<KRec> build_krecs(const std::vector<MaskRec>& masks, const std::vector<uint64_t>& bin_off, int tile_bits,
-                             int nt)
+std::vector<KRec> build_krecs(const std::vector<MaskRec>& masks, const std::vector<uint64_t>& bin_off, int tile_bits)
 {
     const uint32_t row_mask = (1u << tile_bits) - 1u;
-    const uint32_t kmask = row_mask & ~((uint32_t)nt - 1u);
-    const int rpt = (1 << tile_bits) / nt;
     std::vector<KRec> out(masks.size());
     for (size_t i = 0; i < masks.size(); ++i) {
         const MaskRec& m = masks[i];
+        const uint32_t type = m.type_tab >> 28, tab = m.type_tab & 0x0fffffffu;
         KRec k{};
         k.xl = m.x & row_mask;
         k.qpack = m.qpack;
         k.zbase = m.zbase;
-        const uint32_t type = m.type_tab >> 28, tab = m.type_tab & 0x0fffffffu;
-        uint32_t path = PATH_SAME;
-        if (type == MASK_QUAD) {
-            if (m.x & kmask) path = PATH_FULL;
-            else if (m.zbase & kmask) path = PATH_SIGN;
-            for (int r = 0; r < rpt && r < 12; ++r) {
-                const uint32_t ru = (uint32_t)r * (uint32_t)nt;
-                uint32_t ik = 0;
-                for (int j = 0; j < 4; ++j) ik |= ((ru >> mask_q(m.qpack, j)) & 1u) << j;
-                const uint32_t sk = (uint32_t)__builtin_popcount(ru & m.zbase) & 1u;
-                k.kinfo[r / 6] |= (ik | sk << 4) << (5 * (r % 6));
-            }
-        }
-        if (tab >= (1u << 26)) throw Error(SYK_EUNSUPPORTED, "apply_H: too many masks");
-        k.meta = type << 28 | path << 26 | tab;
-        k.pad[0] = (uint32_t)bin_off[i];
-        k.pad[1] = m.x >> tile_bits;
+        k.meta = type << 28 | tab;
+        k.bin0 = (uint32_t)bin_off[i];
+        k.x_high = m.x >> tile_bits;
         out[i] = k;
     }
     return out;
-}
-
-const KRec* krecs_for(const HamiltonianDev& H, const ApplyPlan& P)
-{
-    const int key = P.tile_bits * 4096 + P.nt;
-    auto it = H.krecs.find(key);
-    if (it == H.krecs.end()) {
-        if (H.bin_off->size() != H.host_masks->size()) throw Error(SYK_EINVAL, "apply_H: handle tables incomplete");
-        std::vector<KRec> v = build_krecs(*H.host_masks, *H.bin_off, P.tile_bits, P.nt);
-        std::unique_ptr<DevBuf> b(new DevBuf());
-        b->ensure(v.size() * sizeof(KRec));
-        SYK_HIP(hipMemcpy(b->p, v.data(), v.size() * sizeof(KRec), hipMemcpyHostToDevice));
-        it = H.krecs.emplace(key, std::move(b)).first;
-    }
-    return it->second->as<KRec>();
 }
 
 namespace {

@@ -5,25 +5,18 @@
 
 namespace syk {
 
-// Mask record of the single-vector kernels for one launch shape (tile_bits,
-// threads): everything about a mask that does not depend on the lane or the
-// tile, precomputed on the host.  Loaded with one scalar load.
+// Mask record of the gradient kernel for one launch shape (tile_bits): what
+// a mask needs that does not depend on the lane or the tile.  Loaded with one
+// scalar load.
 struct alignas(16) KRec {
     uint32_t xl;        // x & (tile rows - 1): row offset of the source inside the tile
     uint32_t qpack;     // flipped qubits, one per byte
     uint32_t zbase;     // Z string of the mask
-    uint32_t meta;      // type << 28 | path << 26 | table index
-    uint32_t kinfo[2];  // QUAD, per row k: (index bits from k | sign bit from k << 4) << 5 (k % 6)
-    uint32_t pad[2];    // pad[0]: first derivative bin of the mask; pad[1]: x >> tile_bits
+    uint32_t meta;      // type << 28 | table index
+    uint32_t bin0;      // first derivative bin of the mask
+    uint32_t x_high;    // x >> tile_bits: source tile = tile ^ x_high
 };
 static_assert(sizeof(KRec) == 32, "KRec layout");
-
-// QUAD paths: the table entry and sign of a thread's rows
-enum : uint32_t {
-    PATH_SAME = 0,   // ... are the same for all rows
-    PATH_SIGN = 1,   // ... share the entry; only the sign depends on the row
-    PATH_FULL = 2    // ... both depend on the row
-};
 
 // Mask record of the apply kernel for one launch shape and element size, in
 // the class-sorted order of its chunk (QApplyChunk).  The first four words are
@@ -90,14 +83,9 @@ inline ApplyPlan plan_for(const syk_terms_s& h, int M, int nvec, syk_dtype dtype
 }
 inline ApplyPlan plan_for(const syk_terms_s& h, int nvec, syk_dtype dtype) { return plan_for(h, h.H.M, nvec, dtype); }
 
-struct ApplyPlan;
-// Device mask records for a single-vector launch shape (built on first use).
-const KRec* krecs_for(const HamiltonianDev& H, const ApplyPlan& P);
-
-// Mask records for launch shape (tile_bits, nt), one per mask of `masks` in
-// its order; pad[0] = bin_off[i].
-std::vector<KRec> build_krecs(const std::vector<MaskRec>& masks, const std::vector<uint64_t>& bin_off, int tile_bits,
-                              int nt);
+// Gradient mask records for tiles of 2^tile_bits rows, one per mask of `masks`
+// in its order, with bin0 = bin_off[i].
+std::vector<KRec> build_krecs(const std::vector<MaskRec>& masks, const std::vector<uint64_t>& bin_off, int tile_bits);
 
 // Second row layout: row bits rotated right by tb (bit b -> b - tb mod M), so
 // that the high qubits of the natural layout become the low bits of a tile.

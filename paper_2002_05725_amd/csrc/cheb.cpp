@@ -78,13 +78,20 @@ struct Stepper {
     }
 
     // lam_out = cotangent of the step input; bins += the step's coupling terms.
-    void backward(const ChebOp& op, const void* in, const void* lam, void* lam_out, double* bins)
+    // kept: the step's vectors v_0..v_K from the segment's recomputation, or
+    // NULL to compute them here.
+    void backward(const ChebOp& op, const void* in, const void* lam, void* lam_out, double* bins,
+                  const std::vector<void*>* kept)
     {
         const int K = (int)op.c.size() - 1;
         std::vector<void*> V(K + 1), G(K + 1);
-        for (int k = 0; k <= K; ++k) V[k] = pool.get("V", k);
         for (int k = 1; k <= K; ++k) G[k] = pool.get("G", k);
-        forward(op, in, nullptr, &V);
+        if (kept) {
+            V = *kept;
+        } else {
+            for (int k = 0; k <= K; ++k) V[k] = pool.get("V", k);
+            forward(op, in, nullptr, &V);
+        }
         void* w = pool.get("w");
         c.ops.combine(G[K], lam, 1, std::vector<C>{std::conj(op.c[K])});
         for (int k = K - 1; k >= 0; --k) {
@@ -128,25 +135,56 @@ void chain_forward(Stepper& st, const std::vector<ChebOp>& ops, const void* psi,
 }
 
 // Propagates the cotangent seed back through `ops` (checkpoints from
-// chain_forward) and adds every step's coupling terms into bins.
+// chain_forward) and adds every step's coupling terms into bins.  Each segment
+// between checkpoints is recomputed forward once; with keep_segment (and the
+// memory for it) the Chebyshev vectors of its steps are kept from that pass,
+// else every step computes them again in its reverse sweep.
 void chain_backward(Stepper& st, const std::vector<ChebOp>& ops, const std::string& ckpt_name, const void* seed,
                     double* bins)
 {
     const int Ck = st.s.checkpoint_every;
     const int L = (int)ops.size();
+    const int K = st.s.degree;
+    auto kept_name = [](int j, int k) { return "SV" + std::to_string(j) + "_" + std::to_string(k); };
+    bool keep = st.s.keep_segment != 0;
+    if (keep) {
+        size_t need = 0;
+        for (int j = 0; j < Ck; ++j)
+            for (int k = 0; k <= K; ++k) {
+                const size_t h = st.c.h.ws.held("cheb_" + kept_name(j, k));
+                need += h >= st.pool.bytes ? 0 : st.pool.bytes;
+            }
+        size_t free_b = 0, total_b = 0;
+        SYK_HIP(hipMemGetInfo(&free_b, &total_b));
+        keep = need <= free_b / 2;
+    }
+    std::vector<std::vector<void*>> SV;
+    if (keep) {
+        SV.assign(Ck, std::vector<void*>(K + 1));
+        for (int j = 0; j < Ck; ++j)
+            for (int k = 0; k <= K; ++k) SV[j][k] = st.pool.get(kept_name(j, k));
+    }
     void* lam = st.pool.get("lam0");
     void* lam2 = st.pool.get("lam1");
     st.c.ops.copy(lam, seed);
     const int nseg = (L + Ck - 1) / Ck;
     for (int sg = nseg - 1; sg >= 0; --sg) {
         const int l0 = sg * Ck, l1 = std::min(L, l0 + Ck);
-        // inputs of operations l0 .. l1-1
+        // inputs of operations l0 .. l1-1 (and, kept, every step's vectors)
         st.c.ops.copy(st.pool.get("in", 0), st.pool.get(ckpt_name, sg));
-        for (int l = l0; l + 1 < l1; ++l) apply_op(st, ops[l], st.pool.get("in", l - l0), st.pool.get("in", l - l0 + 1));
+        for (int l = l0; l < l1; ++l) {
+            const bool last = l + 1 == l1;
+            if (!keep || ops[l].maj >= 0) {
+                if (!last) apply_op(st, ops[l], st.pool.get("in", l - l0), st.pool.get("in", l - l0 + 1));
+            } else {
+                st.forward(ops[l], st.pool.get("in", l - l0), last ? nullptr : st.pool.get("in", l - l0 + 1),
+                           &SV[l - l0]);
+            }
+        }
         for (int l = l1 - 1; l >= l0; --l) {
             const void* in = st.pool.get("in", l - l0);
             if (ops[l].maj >= 0) st.c.ops.majorana(ops[l].maj, lam, lam2);   // chi is Hermitian
-            else st.backward(ops[l], in, lam, lam2, bins);
+            else st.backward(ops[l], in, lam, lam2, bins, keep ? &SV[l - l0] : nullptr);
             std::swap(lam, lam2);
         }
     }

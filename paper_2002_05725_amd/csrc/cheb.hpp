@@ -16,6 +16,7 @@ struct ChebSettings {
     int tau_steps;         // steps per imaginary-time leg
     int checkpoint_every;  // stored state every this many operations of a chain
     double e_c, e_h;       // spectrum centre and half-width (fixed: do not move with J)
+    int keep_segment;      // keep a segment's Chebyshev vectors for the reverse sweep when memory allows
 };
 
 // One operation of a chain: a Chebyshev step with coefficients c, or chi_maj.

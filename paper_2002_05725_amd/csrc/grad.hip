@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
                     pr = pi = 0.0;
 #pragma unroll
                     for (int u = 0; u < PP; ++u) {
-                        const c128 x = C.far ? vs[p0 + u][((uint64_t)(tile ^ m.pad[1]) << L.tile_bits) + tid + k * nt]
+                        const c128 x = C.far ? vs[p0 + u][((uint64_t)(tile ^ m.x_high) << L.tile_bits) + tid + k * nt]
                                              : src[u * tile_elems + ((tid + k * nt) ^ m.xl)];
                         pr += gk[u][k].re * x.re + gk[u][k].im * x.im;
                         pi += gk[u][k].re * x.im - gk[u][k].im * x.re;
@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
         for (uint32_t j = C.first; j < C.first + C.count; ++j) {
             const uint32_t lo = local[j];
             const uint32_t hi = (j + 1 < C.first + C.count) ? local[j + 1] : C.bin_count;
-            const uint64_t go = krec[members[j]].pad[0];
+            const uint64_t go = krec[members[j]].bin0;
             for (uint32_t e = tid; e < 2 * (hi - lo); e += nt) mine[2 * go + e] = bins[2 * lo + e];
         }
         __syncthreads();
@@ -533,7 +533,7 @@ void grad_bins(syk_terms_s& h, const std::vector<const void*>& g, const std::vec
                     lm[i] = rotate_mask(T.masks[i], H.M, P.tile_bits);
                     lay[i] = 1;
                 }
-        const std::vector<KRec> kr = build_krecs(lm, T.bin_off, P.tile_bits, P.nt);
+        const std::vector<KRec> kr = build_krecs(lm, T.bin_off, P.tile_bits);
         const GradChunks c = make_grad_chunks(lm, lay, T.bin_off, T.n_bins, P.tile_bits, P.lb);
         const size_t kb = kr.size() * sizeof(KRec), cb = c.chunks.size() * sizeof(GChunk);
         const size_t gb = c.grec.size() * sizeof(GRec), mb = c.members.size() * sizeof(uint32_t);

@@ -23,21 +23,10 @@ struct HamiltonianDev {
     const uint32_t* dz = nullptr;
     const double* dw_d = nullptr;
     const float* dw_f = nullptr;
-    // Group lists for each tile size, built on first use.
+    // Host mask list (sorted by x) and derivative-bin offsets the per-launch-
+    // shape tables are built from.
     const std::vector<MaskRec>* host_masks = nullptr;
     const std::vector<uint64_t>* bin_off = nullptr;
-    mutable std::map<int, std::unique_ptr<DevBuf>> groups;
-    mutable std::map<int, int> n_groups;
-    // Chunks for a tile size; with split_far, QUAD masks that flip only tile
-    // bits are listed separately (far_for).
-    const Group* groups_for(int tile_bits, bool split_far = false) const;
-    int n_groups_for(int tile_bits, bool split_far = false) const;
-    const FarRec* far_for(int tile_bits) const;
-    int n_far_for(int tile_bits) const;
-    mutable std::map<int, std::unique_ptr<DevBuf>> fars;
-    mutable std::map<int, int> n_fars;
-    // Per-launch-shape mask records of the gradient kernel, built on first use.
-    mutable std::map<int, std::unique_ptr<DevBuf>> krecs;
     // Per-launch-shape chunks and class-sorted records of the apply kernel.
     struct ApplyTables {
         DevBuf chunks, recs, far;
@@ -61,6 +50,12 @@ struct Workspace {
         if (!b) b.reset(new DevBuf());
         b->ensure(bytes);
         return b->p;
+    }
+    // bytes already held under `name` (0 if none)
+    size_t held(const std::string& name) const
+    {
+        auto it = bufs.find(name);
+        return (it == bufs.end() || !it->second) ? 0 : it->second->bytes;
     }
     void release_all() { bufs.clear(); }
 };

@@ -214,39 +214,6 @@ void couplings_from_bins(const TermTables& T, const double* bins, double* out)
     }
 }
 
-std::vector<Group> make_groups(const std::vector<MaskRec>& masks, int tile_bits, std::vector<uint32_t>* far)
-{
-    std::vector<Group> g;
-    const uint32_t row_mask = (1u << tile_bits) - 1u;
-    for (uint32_t i = 0; i < (uint32_t)masks.size(); ++i) {
-        const uint32_t xh = masks[i].x >> tile_bits;
-        if (far && (masks[i].type_tab >> 28) == MASK_QUAD && (masks[i].x & row_mask) == 0u) {
-            far->push_back(i);   // all four qubits are tile bits
-            continue;
-        }
-        const bool same = !g.empty() && g.back().x_high == xh;
-        if (!same || g.back().count == (uint32_t)kChunkMasks) {
-            Group c{};
-            c.x_high = xh;
-            c.first = i;
-            c.new_tile = same ? 0u : 1u;
-            c.quad_first = 0xffffffffu;
-            g.push_back(c);
-        }
-        Group& c = g.back();
-        ++c.count;
-        if ((masks[i].type_tab >> 28) == MASK_QUAD) {
-            const uint32_t tab = masks[i].type_tab & 0x0fffffffu;
-            if (c.n_quad == 0) c.quad_first = tab;
-            if (tab != c.quad_first + c.n_quad) throw Error(SYK_EUNSUPPORTED, "QUAD tables not consecutive");
-            ++c.n_quad;
-        }
-    }
-    for (Group& c : g)
-        if (c.n_quad == 0) c.quad_first = 0;
-    return g;
-}
-
 }  // namespace syk
 
 namespace syk {

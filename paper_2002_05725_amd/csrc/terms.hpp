@@ -29,19 +29,9 @@ static_assert(sizeof(MaskRec) == 16, "MaskRec layout");
 
 __host__ __device__ inline uint32_t mask_q(uint32_t qpack, int i) { return (qpack >> (8 * i)) & 0xffu; }
 
-// Masks with the same x >> tile_bits read the same source tile of psi.  The
-// run of such masks is cut into chunks of at most kChunkMasks masks whose
-// QUAD tables fit in LDS next to the source tile.
+// Masks with the same x >> tile_bits read the same source tile of psi; the
+// gradient kernel cuts such runs into chunks of at most kChunkMasks masks.
 constexpr int kChunkMasks = 64;
-struct alignas(16) Group {
-    uint32_t x_high;      // (x >> tile_bits): source tile = tile ^ x_high
-    uint32_t first;       // first mask (index into the sorted mask array)
-    uint32_t count;
-    uint32_t quad_first;  // QUAD table index of the chunk's first QUAD mask
-    uint32_t n_quad;      // QUAD masks in the chunk (their tables are consecutive)
-    uint32_t new_tile;    // x_high differs from the previous chunk's
-    uint32_t pad[2];
-};
 
 // Pauli string X^x Z^z times the phase i^ph (acts as |s> -> i^ph (-1)^{|s&z|} |s^x>).
 struct Pauli {
@@ -114,11 +104,6 @@ void build_sector_tables(const TermTables& full, int s, TermTables& out);
 struct DeviceTerms {
     DevBuf masks, tab4_d, tab4_f, qinfo, phi2_d, phi2_f, w2_d, w2_f, dz, dw_d, dw_f;
 };
-
-// Chunks for tiles of 2^tile_bits rows.  With `far`, QUAD masks that flip no
-// row inside a tile are left out of the chunks and their indices appended to
-// *far instead (their coefficient is constant over a tile).
-std::vector<Group> make_groups(const std::vector<MaskRec>& masks, int tile_bits, std::vector<uint32_t>* far = nullptr);
 
 // A QUAD mask whose flipped qubits are all tile bits.
 struct alignas(16) FarRec {
