@@ -72,6 +72,15 @@ def test_calls_reject_null_handle():
     o = _lib.KrylovOpts(20, 0.1, 0.1, 0.0)
     assert L.syk_otoc(None, 0, 0, 1, 1.0, None, 1, 1, None, None, ctypes.byref(o), None, None, None,
                       None) == _lib.SYK_EINVAL
+    w = np.ones(1)
+    out = np.zeros(4)
+    assert L.syk_coupling_overlaps(None, 1, None, None, w.ctypes.data_as(ctypes.c_void_p),
+                                   out.ctypes.data_as(ctypes.c_void_p), None) == _lib.SYK_EINVAL
+    assert b"handle" in L.syk_last_error()
+    c = _lib.ChebOpts(16, 0.1, 1, 4, 0.0, 2.0, 1)
+    F = ctypes.c_double()
+    assert L.syk_grad_couplings(None, 0, 1, 1.0, 0.2, ctypes.byref(c), None, ctypes.byref(F), None,
+                                None) == _lib.SYK_EINVAL
 
 
 def test_dot_rejects_bad_arguments():
