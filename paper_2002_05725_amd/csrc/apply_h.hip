@@ -200,7 +200,11 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
         __syncthreads();
 
         uint32_t mi = C.first;
-        QRec qn = rec[mi];   // the next QUAD record, loaded one mask ahead (records run one past the end)
+        // The next QUAD record is loaded one mask ahead (records run one past
+        // the end): complex128 at the start of a mask, complex64 after its FMAs
+        // (an outstanding scalar load makes every LDS wait a full wait).
+        constexpr bool kEarlyRecord = sizeof(R) == 8;
+        QRec qn = rec[mi];
         auto class_loop = [&](auto cls) {
             constexpr int CL = decltype(cls)::value;
             constexpr uint32_t XK = (uint32_t)class_bits(CL, KB, 1);   // k bits the masks flip
@@ -208,7 +212,7 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
             const uint32_t n = (C.cnt[CL >> 2] >> (8 * (CL & 3))) & 0xffu;
             for (uint32_t i = 0; i < n; ++i, ++mi) {
                 const QRec q = qn;
-                qn = rec[mi + 1];
+                if constexpr (kEarlyRecord) qn = rec[mi + 1];
                 const uint32_t ia = __builtin_amdgcn_udot4(__builtin_amdgcn_perm(B1, B0, q.sel), kDotW,
                                                            (mi - C.first) * 16u * esz, false);
                 const uint32_t sl = (uint32_t)__popc(tid & q.zl) << 31;
@@ -220,18 +224,32 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
 #pragma unroll
                     for (int b = 0; b < KB; ++b)
                         if ((p >> b) & 1) off += (q.koffs >> (8 * b)) & 0xffu;
-                    const cplx<R> t = tab_at(ia + off);
-                    te[p].re = flip31(t.re, sl);
-                    te[p].im = flip31(t.im, sl);
+                    te[p] = tab_at(ia + off);
                 }
+                // table entries first, then the source rows in row order, so
+                // that each row's FMAs wait only for its own load
+                __builtin_amdgcn_sched_barrier(0);
                 const uint32_t sb = tid_b ^ q.xoff;
+                cplx<R> v[RPT];
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) v[k] = src_at(sb + (((uint32_t)k ^ XK) << kLaneBits) * esz);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int p = 0; p < RPT; ++p) {
+                    if ((p & ~(int)XK) != 0) continue;
+                    te[p].re = flip31(te[p].re, sl);
+                    te[p].im = flip31(te[p].im, sl);
+                }
 #pragma unroll
                 for (int k = 0; k < RPT; ++k) {
                     const cplx<R> t = te[k & (int)XK];
                     const bool neg = (__builtin_popcount((uint32_t)k & ZK) & 1) != 0;
                     const R a = neg ? -t.re : t.re, b = neg ? -t.im : t.im;
-                    const cplx<R> v = src_at(sb + (((uint32_t)k ^ XK) << kLaneBits) * esz);
-                    cmac(pr[k], pi[k], a, b, v);
+                    cmac(pr[k], pi[k], a, b, v[k]);
+                }
+                if constexpr (!kEarlyRecord) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    qn = rec[mi + 1];
                 }
             }
         };
