@@ -353,3 +353,29 @@ def test_batched_otoc_disorder_average():
                                                times)
         assert np.abs(F[:, c] - Fr).max() <= 1e-10 * np.abs(Fr).max()
         assert abs(Z[c] - Zr) <= 1e-10 * Zr
+
+
+def test_batched_otoc_full_block_n36():
+    """The disorder-averaging workload at its block shape: N=36, 32 realisations
+    x 2 typical states in one 64-column block, beta=5, t in [0, 12].  complex64
+    block vs complex128 block to 2e-5 (FP64 inner products, complex64 states);
+    a sampled column of the complex128 block vs a single-column call on its own
+    realisation (1e-12)."""
+    N, R = 36, 32
+    _say("batched OTOC block N=36, 64 columns")
+    Js = np.stack([inputs.couplings(N, inputs.batch_coupling_seed(N, r)) for r in range(R)])
+    psis = np.stack([inputs.typical_state(N, inputs.batch_state_seed(N, r, s)) for r in range(R) for s in range(2)])
+    real = np.repeat(np.arange(R), 2)
+    times = [0.0, 6.0, 12.0]
+    T = api.Terms(N, Js)
+    F, _, Z = api.otoc(T, 0, 1, 5.0, times, _gpu(psis), m=16, dt=0.5, tau_step=0.625, real_of_col=real)
+    F64, _, _ = api.otoc(T, 0, 1, 5.0, times, _gpu(psis, torch.complex64), m=16, dt=0.5, tau_step=0.625,
+                         real_of_col=real)
+    assert np.abs(F64 - F).max() <= 2e-5
+    for c in (37,):
+        Tc = api.Terms(N, Js[real[c]])
+        Fc, _, Zc = api.otoc(Tc, 0, 1, 5.0, times, _gpu(psis[c]), m=16, dt=0.5, tau_step=0.625)
+        assert np.abs(F[:, c] - Fc[:, 0]).max() <= 1e-12 * max(1.0, np.abs(Fc).max())
+        assert abs(Z[c] - Zc[0]) <= 1e-12 * Zc[0]
+        Tc.close()
+    T.close()
