@@ -166,7 +166,9 @@ def main():
     ap.add_argument("--N", type=int, default=52)
     ap.add_argument("--m", type=int, default=12)
     ap.add_argument("--dt", type=float, default=0.25)
-    ap.add_argument("--c64-steps", type=int, default=1)
+    ap.add_argument("--c64-steps", type=int, default=2,
+                    help="timed complex64 steps after one warmup step; when 1 + this equals the complex128 "
+                         "leg's warmup + steps, the two final states are compared")
     ap.add_argument("--sector-steps", type=int, default=1,
                     help="time steps of the parity-sector leg (complex128, half-size state; 0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -228,7 +230,6 @@ def main():
 
     c64 = None
     if args.c64_steps > 0:
-        del psi
         torch.cuda.empty_cache()
         p64 = torch.from_numpy(psi_host).to(dev).to(torch.complex64)
         log(f"[bench] complex64: 1 warmup + {args.c64_steps} timed steps")
@@ -243,9 +244,16 @@ def main():
         c64["apply_pct_hbm_peak"] = 100 * c64["apply_alg_GBps"] / HBM_PEAK_GBS
         c64["apply_TFLOPs"] = FLOPS_PER_PAIR * T.n_masks * D / a64 / 1e12
         c64["apply_frac_fp32_vector_peak"] = c64["apply_TFLOPs"] / FP32_VECTOR_PEAK_TFLOPS
+        # precision of the complex64 form: both legs propagated the same state
+        # by the same number of steps
+        if 1 + args.c64_steps == args.warmup + args.steps:
+            diff = torch.linalg.vector_norm(p64.to(torch.complex128) - psi).item()
+            c64["rel_state_error_vs_c128"] = diff / torch.linalg.vector_norm(psi).item()
+            c64["steps_compared"] = 1 + args.c64_steps
         del p64
         log(f"[bench] c64: {c64['ms_per_step']:.0f} ms/step, apply {a64 * 1e3:.1f} ms")
 
+    del psi
     sector = None
     if args.sector_steps > 0:
         torch.cuda.empty_cache()
