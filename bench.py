@@ -112,6 +112,50 @@ def batched_leg(api, inputs, torch, np, dev, N, m, dt):
     return out
 
 
+def n60_leg(api, inputs, torch, dev):
+    """Largest single-GPU size: N=60 (dim 2^30, 487,635 couplings, 16 GiB per
+    complex128 state): one apply_H in each precision and one Lanczos step of two
+    iterations (complex128), on a seeded random state drawn on the device."""
+    N = 60
+    T = api.Terms(N, inputs.couplings(N, 0))
+    out = {"N": N, "dim": T.dim, "n_masks": T.n_masks}
+    g = torch.Generator(device=dev).manual_seed(1)
+    x = torch.randn(T.dim, dtype=torch.complex128, device=dev, generator=g)
+    x /= torch.linalg.vector_norm(x)
+    y = torch.empty_like(x)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        api.timing_reset()
+        api.timing_enable(True)
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        api.timing_enable(False)
+        n, ms = api.timing_read()
+        api.timing_reset()
+        return wall, n, ms
+
+    api.apply_H(T, x, y)   # first call: launch tables and the diagonal of H
+    _, n, ms = timed(lambda: api.apply_H(T, x, y))
+    out["apply_c128_ms"] = ms / n
+    wall, _, _ = timed(lambda: api.krylov_expmv(T, x, -1j, 0.01, m=2, dt=0.01))
+    out["lanczos_m2_c128_s"] = wall
+    del y
+    x64 = x.to(torch.complex64)
+    del x
+    torch.cuda.empty_cache()
+    y64 = torch.empty_like(x64)
+    api.apply_H(T, x64, y64)
+    _, n, ms = timed(lambda: api.apply_H(T, x64, y64))
+    out["apply_c64_ms"] = ms / n
+    del x64, y64
+    T.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def grad_leg(api, inputs, torch, dev, N, t_star, degree, dt, beta):
     """Cost of dF/dJ for every coupling against the Chebyshev forward alone."""
     J = inputs.couplings(N, 0)
@@ -177,6 +221,7 @@ def main():
     ap.add_argument("--grad-N", type=int, default=44, help="size of the gradient leg (0: skip)")
     ap.add_argument("--grad-t", type=float, default=0.5,
                     help="t* of the gradient leg (a multiple of dt = 0.1; the cost ratio barely depends on it)")
+    ap.add_argument("--no-n60", action="store_true", help="skip the N=60 leg (dim 2^30)")
     ap.add_argument("--profile-apply", type=int, default=0,
                     help="only run this many complex128 apply_H calls and one 1 GiB device copy "
                          "(for hardware-counter runs), then exit")
@@ -291,6 +336,17 @@ def main():
         grad = grad_leg(api, inputs, torch, dev, args.grad_N, args.grad_t, 32, 0.1, 5.0)
         log(f"[bench] grad/fwd = {grad['grad_fwd_ratio']:.2f}")
 
+    n60 = None
+    if not args.no_n60:
+        torch.cuda.empty_cache()
+        log("[bench] N=60 leg: one apply_H per precision, one m=2 Lanczos step")
+        try:
+            n60 = n60_leg(api, inputs, torch, dev)
+            log(f"[bench] N=60: apply {n60['apply_c128_ms']:.0f} ms (c128), {n60['apply_c64_ms']:.0f} ms (c64)")
+        except (RuntimeError, MemoryError) as e:   # reported, not fatal to the headline
+            n60 = {"error": str(e)[:300]}
+            log(f"[bench] N=60 leg failed: {e}")
+
     traffic = traffic_from_profile(f"N{N}_c128")
     out = {
         "metric": METRIC,
@@ -336,6 +392,7 @@ def main():
         "batched": batched,
         "gradient": grad,
         "grad_fwd_ratio": grad["grad_fwd_ratio"] if grad else None,
+        "n60": n60,
     }
     if not args.no_cpu_baseline:
         log("[bench] CPU checker baseline")
