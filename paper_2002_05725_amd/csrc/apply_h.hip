@@ -14,6 +14,8 @@
 // (scalar loads) and the chunk's QUAD tables are staged into LDS next to the
 // source tile.  Up to 64 columns per launch.
 #include <algorithm>
+#include <map>
+#include <tuple>
 #include <utility>
 
 #include "apply_h.hpp"
@@ -115,7 +117,7 @@ __device__ __forceinline__ void cmac(R& pr, R& pi, R a, R b, const cplx<R>& v)
 }
 
 template <typename R, int RPT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 && RPT == 8 ? 4 : 1)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RPT == 8 ? 4 : 1)))
 k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
                                                const QRec* __restrict__ rec, KLayout L,
                                                const cplx<R>* __restrict__ psi, cplx<R>* __restrict__ out)
@@ -205,6 +207,73 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
         // (an outstanding scalar load makes every LDS wait a full wait).
         constexpr bool kEarlyRecord = sizeof(R) == 8;
         QRec qn = rec[mi];
+        // Groups of three QUAD masks (same lane flips, J = 1 or 2 flipped k
+        // bits in all three ways): the lane index, the lane sign and the source
+        // rows are read once for the three.  Member j's table is the (m + j)-th
+        // of the chunk; the index bits of its flipped k bits sit at kof and
+        // 2 kof (kof: the first record's koffs).  The next member's table
+        // entries are read while the previous member's FMAs run.
+        if constexpr (KB == kMaxKBits) {
+            auto group_loop = [&](auto gcls) {
+                constexpr int GC = decltype(gcls)::value;
+                constexpr int J = 1 + (GC >> 1), P = GC & 1;
+                constexpr int NE = 1 << J;   // table entries per member
+                const uint32_t n = (C.cnt[(kQuadClasses + GC) >> 2] >> (8 * ((kQuadClasses + GC) & 3))) & 0xffu;
+                for (uint32_t i = 0; i < n; ++i, mi += 3) {
+                    const QRec q = qn;
+                    if constexpr (kEarlyRecord) qn = rec[mi + 3];
+                    const uint32_t ia = __builtin_amdgcn_udot4(__builtin_amdgcn_perm(B1, B0, q.sel), kDotW,
+                                                               (mi - C.first) * 16u * esz, false);
+                    const uint32_t sl = (uint32_t)__popc(tid & q.zl) << 31;
+                    const uint32_t kof = q.koffs;
+                    auto load_member = [&](auto jc, cplx<R> (&t)[NE]) {
+                        constexpr uint32_t j = decltype(jc)::value;
+#pragma unroll
+                        for (int e = 0; e < NE; ++e)
+                            t[e] = tab_at(ia + (uint32_t)e * kof + j * 16u * esz);
+                    };
+                    auto member_fma = [&](auto jc, cplx<R> (&t)[NE], const cplx<R> (&v)[RPT]) {
+                        constexpr int j = decltype(jc)::value;
+                        constexpr int XK = group_xk(J, j), ZK = group_zk(XK, P);
+#pragma unroll
+                        for (int e = 0; e < NE; ++e) {
+                            t[e].re = flip31(t[e].re, sl);
+                            t[e].im = flip31(t[e].im, sl);
+                        }
+#pragma unroll
+                        for (int k = 0; k < RPT; ++k) {
+                            const cplx<R> te = t[pack_bits3(k & XK, XK)];
+                            const bool neg = (popc3(k & ZK) & 1) != 0;
+                            const R a = neg ? -te.re : te.re, b = neg ? -te.im : te.im;
+                            cmac(pr[k], pi[k], a, b, v[k ^ XK]);
+                        }
+                    };
+                    using I0 = std::integral_constant<int, 0>;
+                    using I1 = std::integral_constant<int, 1>;
+                    using I2 = std::integral_constant<int, 2>;
+                    cplx<R> ta[NE], tb[NE];
+                    load_member(I0{}, ta);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const uint32_t sb = tid_b ^ q.xoff;
+                    cplx<R> v[RPT];
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) v[k] = src_at(sb + ((uint32_t)k << kLaneBits) * esz);
+                    __builtin_amdgcn_sched_barrier(0);
+                    load_member(I1{}, tb);
+                    member_fma(I0{}, ta, v);
+                    __builtin_amdgcn_sched_barrier(0);
+                    load_member(I2{}, ta);
+                    member_fma(I1{}, tb, v);
+                    __builtin_amdgcn_sched_barrier(0);
+                    member_fma(I2{}, ta, v);
+                    if constexpr (!kEarlyRecord) {
+                        __builtin_amdgcn_sched_barrier(0);
+                        qn = rec[mi + 3];
+                    }
+                }
+            };
+            for_each_class(group_loop, std::make_integer_sequence<int, kQuadGroupClasses>{});
+        }
         auto class_loop = [&](auto cls) {
             constexpr int CL = decltype(cls)::value;
             constexpr uint32_t XK = (uint32_t)class_bits(CL, KB, 1);   // k bits the masks flip
@@ -525,7 +594,7 @@ void launch_t(const ApplyPlan& P, const KTerms<R>& T, const QApplyChunk* chunks,
 // rows, 2^lane_bits threads and elements of esz bytes.  masks must be sorted by
 // x; QUAD masks that neither flip nor sign-depend on a row bit inside a tile go
 // to the far list.
-void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int lane_bits, uint32_t esz,
+void build_apply_tables(const std::vector<MaskRec>& masks_in, int tile_bits, int lane_bits, uint32_t esz,
                         std::vector<QApplyChunk>& chunks, std::vector<QRec>& recs, std::vector<FarRec>& far)
 {
     const uint32_t row_mask = (1u << tile_bits) - 1u;
@@ -535,6 +604,7 @@ void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int la
     const uint32_t kbits_mask = (1u << kb) - 1u;
     auto quad_class_of = [&](const MaskRec& m) { return quad_class(m.x, m.zbase, lane_bits, kb); };
     auto type_of = [](const MaskRec& m) { return m.type_tab >> 28; };
+    auto xk_of = [&](const MaskRec& m) { return (m.x >> lane_bits) & kbits_mask; };
     // PAIR masks flipping no k bit, and the k-bit pattern of their Z string
     auto is_k_bit = [&](uint32_t q) { return q >= (uint32_t)lane_bits && q < (uint32_t)tile_bits; };
     auto flat_pair = [&](const MaskRec& m) {
@@ -543,6 +613,16 @@ void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int la
     auto zk_of = [&](const MaskRec& m) { return (int)((m.zbase >> lane_bits) & kbits_mask); };
     // table slots (16 entries each) a mask stages
     auto slots_of = [&](const MaskRec& m) { return type_of(m) == MASK_DIAG ? 0u : 1u; };
+    // Inside a run of one x_high: by lane flips, then by k flips, so that the
+    // masks of a group are adjacent (a chunk boundary rarely splits one).
+    std::vector<MaskRec> masks = masks_in;
+    std::stable_sort(masks.begin(), masks.end(), [&](const MaskRec& a, const MaskRec& b) {
+        const uint32_t ha = a.x >> tile_bits, hb = b.x >> tile_bits;
+        if (ha != hb) return ha < hb;
+        const uint32_t la = a.x & lane_mask, lb2 = b.x & lane_mask;
+        if (la != lb2) return la < lb2;
+        return xk_of(a) < xk_of(b);
+    });
     size_t i = 0;
     uint32_t prev_high = 0xffffffffu;
     while (i < masks.size()) {
@@ -564,20 +644,12 @@ void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int la
             ++i;
         }
         if (mem.empty()) continue;
-        auto key = [&](uint32_t j) {
-            const MaskRec& m = masks[j];
-            const uint32_t t = type_of(m);
-            return t == MASK_QUAD ? quad_class_of(m) : t == MASK_PAIR ? (flat_pair(m) ? 100 + zk_of(m) : 150) : 200;
-        };
-        std::stable_sort(mem.begin(), mem.end(), [&](uint32_t a, uint32_t b) { return key(a) < key(b); });
-        QApplyChunk c{};
-        c.x_high = xh;
-        c.first = (uint32_t)recs.size();
-        c.new_tile = (xh != prev_high) ? 1u : 0u;
-        prev_high = xh;
-        uint32_t slot = 0;
-        for (uint32_t j : mem) {
-            const MaskRec& m = masks[j];
+        const size_t nm = mem.size();
+        // records (the PAIR / DIAG table offsets follow the final order)
+        std::vector<QRec> rr(nm);
+        std::vector<int> key(nm);
+        for (size_t u = 0; u < nm; ++u) {
+            const MaskRec& m = masks[mem[u]];
             const uint32_t t = type_of(m);
             QRec r{};
             r.zl = m.zbase & lane_mask;
@@ -587,18 +659,105 @@ void build_apply_tables(const std::vector<MaskRec>& masks, int tile_bits, int la
             r.qpack = m.qpack;
             r.zbase = m.zbase;
             if (t == MASK_QUAD) {
-                const int cls = quad_class_of(m);
-                ++c.n_quad;
-                c.cnt[cls >> 2] += 1u << (8 * (cls & 3));
                 for (int q = 0; q < 4; ++q) {
                     const uint32_t qb = mask_q(m.qpack, q);
                     r.sel |= (qb < (uint32_t)lane_bits ? qb : 0x0cu) << (8 * q);
                     const int b = (int)qb - lane_bits;
                     if (b >= 0 && b < kb) r.koffs |= ((1u << q) * esz) << (8 * b);
                 }
+                key[u] = 1000 + quad_class_of(m);
+            } else {
+                r.koffs = (m.x >> lane_bits) & kbits_mask;
+                key[u] = t == MASK_PAIR ? (flat_pair(m) ? 2000 + zk_of(m) : 2500) : 3000;
+            }
+            rr[u] = r;
+        }
+        // Groups: three QUAD masks with the same lane flips that flip J = 1 or
+        // 2 k bits in all three ways, whose classes are those of a group class
+        // and whose records agree on what the kernel reads once per group.
+        std::vector<int> gcls(nm, -1), gid(nm, 0), gpos(nm, 0);
+        uint32_t group_kof[256] = {};
+        int ng = 0;
+        if (kb == kMaxKBits) {
+            std::map<std::pair<uint32_t, int>, std::vector<size_t>> cand;
+            for (size_t u = 0; u < nm; ++u) {
+                const MaskRec& m = masks[mem[u]];
+                const int J = __builtin_popcount(xk_of(m));
+                if (type_of(m) == MASK_QUAD && (J == 1 || J == 2)) cand[{m.x & lane_mask, J}].push_back(u);
+            }
+            for (const auto& kv : cand) {
+                const int J = kv.first.second;
+                const std::vector<size_t>& v = kv.second;
+                if (v.size() != 3) continue;
+                size_t mj[3];
+                bool ok = true;
+                for (int j = 0; j < 3 && ok; ++j) {
+                    ok = false;
+                    for (size_t u : v)
+                        if ((int)xk_of(masks[mem[u]]) == group_xk(J, j)) {
+                            mj[j] = u;
+                            ok = true;
+                        }
+                }
+                if (!ok) continue;
+                int gc = -1;
+                for (int P = 0; P < 2 && gc < 0; ++P) {
+                    const int g = 2 * (J - 1) + P;
+                    bool all = true;
+                    for (int j = 0; j < 3; ++j) all = all && quad_class_of(masks[mem[mj[j]]]) == group_member_class(g, j);
+                    if (all) gc = g;
+                }
+                if (gc < 0) continue;
+                const QRec& r0 = rr[mj[0]];
+                const uint32_t kof = r0.koffs & 0xffu;   // index-bit offset of member 0's lowest flipped k bit
+                ok = kof != 0u;
+                for (int j = 0; j < 3 && ok; ++j) {
+                    const QRec& r = rr[mj[j]];
+                    ok = r.sel == r0.sel && r.zl == r0.zl && r.xoff == r0.xoff;
+                    uint32_t want = 0, t = 0;
+                    for (int b = 0; b < kMaxKBits; ++b)
+                        if ((group_xk(J, j) >> b) & 1) want |= (kof << t++) << (8 * b);
+                    ok = ok && r.koffs == want;
+                }
+                if (!ok) continue;
+                for (int j = 0; j < 3; ++j) {
+                    gcls[mj[j]] = gc;
+                    gid[mj[j]] = ng;
+                    gpos[mj[j]] = j;
+                }
+                group_kof[ng++] = kof;
+            }
+        }
+        std::vector<size_t> ord(nm);
+        for (size_t u = 0; u < nm; ++u) ord[u] = u;
+        auto okey = [&](size_t u) {
+            return gcls[u] >= 0 ? std::make_tuple(gcls[u], gid[u], gpos[u]) : std::make_tuple(key[u], 0, 0);
+        };
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return okey(a) < okey(b); });
+        QApplyChunk c{};
+        c.x_high = xh;
+        c.first = (uint32_t)recs.size();
+        c.new_tile = (xh != prev_high) ? 1u : 0u;
+        prev_high = xh;
+        uint32_t slot = 0;
+        for (size_t u : ord) {
+            const MaskRec& m = masks[mem[u]];
+            const uint32_t t = type_of(m);
+            QRec r = rr[u];
+            if (t == MASK_QUAD) {
+                ++c.n_quad;
+                if (gcls[u] >= 0) {
+                    if (gpos[u] == 0) {
+                        const int g = kQuadClasses + gcls[u];
+                        c.cnt[g >> 2] += 1u << (8 * (g & 3));
+                        r.koffs = group_kof[gid[u]];
+                    }
+                } else {
+                    const int cls = quad_class_of(m);
+                    c.cnt[cls >> 2] += 1u << (8 * (cls & 3));
+                }
             } else {
                 r.sel = slot * 16u * esz;
-                r.koffs = (m.x >> lane_bits) & kbits_mask;
                 if (t == MASK_PAIR) {
                     ++c.n_pair;
                     if (flat_pair(m)) {

@@ -27,7 +27,8 @@ struct alignas(16) QRec {
                      // PAIR: byte offset of the mask's staged values in the chunk's table area
     uint32_t zl;     // lane bits of zbase
     uint32_t xoff;   // (x & lane mask) * element size: lane part of the source offset
-    uint32_t koffs;  // QUAD: byte b = table byte offset of the index bit that k-bit b sets (0 if b is not flipped);
+    uint32_t koffs;  // QUAD: byte b = table byte offset of the index bit that k-bit b sets (0 if b is not flipped),
+                     // except in the first record of a group: the offset of its lowest flipped k bit;
                      // PAIR / DIAG: the k bits of x
     uint32_t tab;    // index into the type's tables
     uint32_t xl;     // x & (tile rows - 1)
@@ -39,9 +40,10 @@ static_assert(sizeof(QRec) == 32, "QRec layout");
 constexpr int kMaxKBits = 3;   // up to 8 rows per thread
 constexpr int kQuadClasses = 27;   // 3^kMaxKBits (k-bit flipped / in the Z string / neither)
 
-// One chunk of the apply kernel: masks sharing a source tile, QUAD masks first,
-// sorted by class, then PAIR (those that flip no k bit first, sorted by the k
-// bits of their Z string), then DIAG.
+// One chunk of the apply kernel: masks sharing a source tile, QUAD masks first
+// (groups of three by group class, then the others sorted by class), then PAIR
+// (those that flip no k bit first, sorted by the k bits of their Z string),
+// then DIAG.
 struct alignas(16) QApplyChunk {
     uint32_t x_high;    // source tile = tile ^ x_high
     uint32_t first;     // first record (index into the QRec array)
@@ -49,7 +51,7 @@ struct alignas(16) QApplyChunk {
     uint32_t n_quad;
     uint32_t n_pair, n_diag;
     uint32_t pcnt[2];   // PAIR masks that flip no k bit, per k-bit pattern of zbase, one byte per pattern
-    uint32_t cnt[8];    // QUAD masks per class, one byte per class
+    uint32_t cnt[8];    // byte c < 27: QUAD masks of class c outside groups; byte 27 + g: groups of class g
 };
 static_assert(sizeof(QApplyChunk) == 64, "QApplyChunk layout");
 
