@@ -259,13 +259,24 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
 #pragma unroll
                     for (int k = 0; k < RPT; ++k) v[k] = src_at(sb + ((uint32_t)k << kLaneBits) * esz);
                     __builtin_amdgcn_sched_barrier(0);
-                    load_member(I1{}, tb);
-                    member_fma(I0{}, ta, v);
-                    __builtin_amdgcn_sched_barrier(0);
-                    load_member(I2{}, ta);
-                    member_fma(I1{}, tb, v);
-                    __builtin_amdgcn_sched_barrier(0);
-                    member_fma(I2{}, ta, v);
+                    if constexpr (J == 1) {
+                        load_member(I1{}, tb);
+                        member_fma(I0{}, ta, v);
+                        __builtin_amdgcn_sched_barrier(0);
+                        load_member(I2{}, ta);
+                        member_fma(I1{}, tb, v);
+                        __builtin_amdgcn_sched_barrier(0);
+                        member_fma(I2{}, ta, v);
+                    } else {
+                        // four entries per member: no read-ahead (register pressure)
+                        member_fma(I0{}, ta, v);
+                        __builtin_amdgcn_sched_barrier(0);
+                        load_member(I1{}, tb);
+                        member_fma(I1{}, tb, v);
+                        __builtin_amdgcn_sched_barrier(0);
+                        load_member(I2{}, ta);
+                        member_fma(I2{}, ta, v);
+                    }
                     if constexpr (!kEarlyRecord) {
                         __builtin_amdgcn_sched_barrier(0);
                         qn = rec[mi + 3];
