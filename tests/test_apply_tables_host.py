@@ -2,9 +2,10 @@
 
 tests/host/apply_tables_emu.cpp builds the tables with the library's host code
 (both row layouts, complex128 and complex64 chunk sizes, 8 rows per thread) and
-evaluates the QUAD part of H psi from them the way k_apply reads them: groups of
-three masks sharing their source rows, then single masks by row class.  It
-compares with the direct sum over the QUAD masks.  The kernel source is
+evaluates H psi from them the way k_apply reads them: groups of three QUAD
+masks sharing their source rows, single QUAD masks by row class, PAIR masks
+(flat and row by row, from their staged row forms) and the diagonal.  It
+compares with the direct sum over the term tables.  The kernel source is
 compiled with hipcc (device code included); nothing runs on a GPU.
 """
 import os
