@@ -11,7 +11,9 @@
 // result is compared with the direct sum over the term tables:
 // (-1)^{|r & zbase|} T_x[bits of r at the flipped qubits] psi[r ^ x] (QUAD),
 // (-1)^{|r & zbase|} sum_e Phi[bits at q0, q1][e] L_e(r) psi[r ^ x] (PAIR),
-// sum_n d_n (-1)^{|r & z_n|} psi[r] (DIAG).
+// sum_n d_n (-1)^{|r & z_n|} psi[r] (DIAG).  For the parity sectors the same is
+// done on the sector tables, whose direct sum is first compared with the full
+// H applied to the sector state embedded in the full space.
 //
 // Exit status 0 when every case agrees to 1e-12 relative and groups were found
 // where the sizes allow them; one line per case on stdout.
@@ -26,16 +28,56 @@ typedef std::complex<double> C;
 
 namespace {
 
-int run_case(int N, int tb, bool two, uint32_t esz)
+// The direct sum over a set of term tables on M qubits (n_real = 1).
+std::vector<C> direct_apply(const TermTables& T, int M, const std::vector<C>& psi)
 {
-    std::mt19937_64 g((uint64_t)N * 131 + esz + (two ? 7 : 0));
+    const uint64_t D = 1ull << M;
+    std::vector<C> out(D, 0.0);
+    for (uint64_t r = 0; r < D; ++r)
+        for (const MaskRec& m : T.masks) {
+            const uint32_t type = m.type_tab >> 28, tab = m.type_tab & 0x0fffffffu;
+            const double sg = (__builtin_popcount((uint32_t)r & m.zbase) & 1) ? -1.0 : 1.0;
+            if (type == MASK_QUAD) {
+                int idx = 0;
+                for (int k = 0; k < 4; ++k) idx |= (int)((r >> mask_q(m.qpack, k)) & 1u) << k;
+                const c128 t = T.tab4[(size_t)tab * 16 + idx];
+                out[r] += sg * C(t.re, t.im) * psi[r ^ m.x];
+            } else if (type == MASK_PAIR) {
+                const int idx = (int)((r >> mask_q(m.qpack, 0)) & 1u) | (int)((r >> mask_q(m.qpack, 1)) & 1u) << 1;
+                C d = 0.0;
+                for (int e = 0; e < 4; ++e) {
+                    const double* w = &T.w2[((size_t)tab * 4 + e) * (M + 1)];
+                    double Le = w[M];
+                    for (int c = 0; c < M; ++c) Le += w[c] * (double)((r >> c) & 1u);
+                    const c128 ph = T.phi2[(size_t)tab * 16 + idx * 4 + e];
+                    d += C(ph.re, ph.im) * Le;
+                }
+                out[r] += sg * d * psi[r ^ m.x];
+            } else {
+                double d = 0.0;
+                for (int n = 0; n < T.n_diag; ++n)
+                    d += (__builtin_popcount((uint32_t)r & T.dz[n]) & 1) ? -T.dw[n] : T.dw[n];
+                out[r] += d * psi[r];
+            }
+        }
+    return out;
+}
+
+// sector < 0: the full tables of N Majoranas; sector 0 / 1: the tables of that
+// fermion-parity sector (M - 1 qubits), which are first checked against the
+// full H on the embedded state.
+int run_case(int N, int tb, bool two, uint32_t esz, int sector)
+{
+    std::mt19937_64 g((uint64_t)N * 131 + esz + (two ? 7 : 0) + 1000 * (uint64_t)(sector + 1));
     std::normal_distribution<double> nd;
     const int nc = N * (N - 1) * (N - 2) * (N - 3) / 24;
     std::vector<double> J(nc);
     for (double& v : J) v = nd(g) * 0.1;
-    TermTables T;
-    build_tables(N, 1, J.data(), T);
-    const int M = N / 2;
+    TermTables TF, TS;
+    build_tables(N, 1, J.data(), TF);
+    if (sector >= 0) build_sector_tables(TF, sector, TS);
+    const TermTables& T = sector >= 0 ? TS : TF;
+    const int M = sector >= 0 ? N / 2 - 1 : N / 2;
     const uint64_t D = 1ull << M;
     const uint32_t rows = 1u << tb;
     std::vector<C> psi(D);
@@ -47,31 +89,22 @@ int run_case(int N, int tb, bool two, uint32_t esz)
         return d;
     };
     auto wrow = [&](uint32_t tab, int e) { return &T.w2[((size_t)tab * 4 + e) * (M + 1)]; };
-    std::vector<C> ref(D, 0.0);
-    for (uint64_t r = 0; r < D; ++r)
-        for (const MaskRec& m : T.masks) {
-            const uint32_t type = m.type_tab >> 28, tab = m.type_tab & 0x0fffffffu;
-            const double sg = (__builtin_popcount((uint32_t)r & m.zbase) & 1) ? -1.0 : 1.0;
-            if (type == MASK_QUAD) {
-                int idx = 0;
-                for (int k = 0; k < 4; ++k) idx |= (int)((r >> mask_q(m.qpack, k)) & 1u) << k;
-                const c128 t = T.tab4[(size_t)tab * 16 + idx];
-                ref[r] += sg * C(t.re, t.im) * psi[r ^ m.x];
-            } else if (type == MASK_PAIR) {
-                const int idx = (int)((r >> mask_q(m.qpack, 0)) & 1u) | (int)((r >> mask_q(m.qpack, 1)) & 1u) << 1;
-                C d = 0.0;
-                for (int e = 0; e < 4; ++e) {
-                    const double* w = wrow(tab, e);
-                    double Le = w[M];
-                    for (int c = 0; c < M; ++c) Le += w[c] * (double)((r >> c) & 1u);
-                    const c128 ph = T.phi2[(size_t)tab * 16 + idx * 4 + e];
-                    d += C(ph.re, ph.im) * Le;
-                }
-                ref[r] += sg * d * psi[r ^ m.x];
-            } else {
-                ref[r] += diag_at(r) * psi[r];
-            }
+    const std::vector<C> ref = direct_apply(T, M, psi);
+    double sector_err = 0.0;
+    if (sector >= 0) {
+        // sector row u is the full row u + 2^M (parity(u) ^ s); H keeps the parity
+        auto full_row = [&](uint64_t u) { return u + ((uint64_t)((__builtin_popcountll(u) & 1) ^ sector) << M); };
+        std::vector<C> pf(2 * D, 0.0);
+        for (uint64_t u = 0; u < D; ++u) pf[full_row(u)] = psi[u];
+        const std::vector<C> hf = direct_apply(TF, M + 1, pf);
+        double e = 0.0, off = 0.0, mx = 0.0;
+        for (uint64_t u = 0; u < D; ++u) {
+            e = std::max(e, std::abs(hf[full_row(u)] - ref[u]));
+            off = std::max(off, std::abs(hf[full_row(u) ^ (1ull << M)]));   // the other sector's row
+            mx = std::max(mx, std::abs(ref[u]));
         }
+        sector_err = std::max(e, off) / mx;
+    }
 
     std::vector<C> out(D, 0.0);
     int groups = 0, bad_layout = 0;
@@ -265,10 +298,10 @@ int run_case(int N, int tb, bool two, uint32_t esz)
         mx = std::max(mx, std::abs(ref[r]));
     }
     const double rel = err / mx;
-    std::printf("N=%d tile_bits=%d layouts=%d esz=%u groups(tile 0)=%d rel_err=%.3e table_errors=%d\n", N, tb,
-                two ? 2 : 1, esz, groups, rel, bad_layout);
+    std::printf("N=%d sector=%d tile_bits=%d layouts=%d esz=%u groups(tile 0)=%d rel_err=%.3e sector_err=%.3e "
+                "table_errors=%d\n", N, sector, tb, two ? 2 : 1, esz, groups, rel, sector_err, bad_layout);
     std::fflush(stdout);
-    return (rel < 1e-12 && groups > 0 && bad_layout == 0) ? 0 : 1;
+    return (rel < 1e-12 && sector_err < 1e-12 && groups > 0 && bad_layout == 0) ? 0 : 1;
 }
 
 }  // namespace
@@ -278,6 +311,10 @@ int main()
     int bad = 0;
     for (int N : {22, 24, 28})
         for (bool two : {false, true})
-            for (uint32_t esz : {16u, 8u}) bad += run_case(N, 11, two, esz);
+            for (uint32_t esz : {16u, 8u}) bad += run_case(N, 11, two, esz, -1);
+    // parity sectors (M - 1 qubits)
+    for (int s : {0, 1})
+        for (bool two : {false, true}) bad += run_case(24, 11, two, 16u, s);
+    bad += run_case(28, 11, true, 8u, 1);
     return bad;
 }

@@ -5,8 +5,11 @@ tests/host/apply_tables_emu.cpp builds the tables with the library's host code
 evaluates H psi from them the way k_apply reads them: groups of three QUAD
 masks sharing their source rows, single QUAD masks by row class, PAIR masks
 (flat and row by row, from their staged row forms) and the diagonal.  It
-compares with the direct sum over the term tables.  The kernel source is
-compiled with hipcc (device code included); nothing runs on a GPU.
+compares with the direct sum over the term tables, for the full space and for
+both fermion-parity sectors, whose tables (M - 1 qubits, implied top qubit) are
+first compared with the full H on the sector state embedded in the full space.
+The kernel source is compiled with hipcc (device code included); nothing runs
+on a GPU.
 """
 import os
 import subprocess
@@ -33,4 +36,5 @@ def test_apply_tables_match_direct_quad_sum(tmp_path):
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr[-2000:]
     lines = [ln for ln in r.stdout.splitlines() if ln.startswith("N=")]
-    assert len(lines) == 12
+    assert len(lines) == 17
+    assert sum("sector=0" in ln for ln in lines) == 2 and sum("sector=1" in ln for ln in lines) == 3
