@@ -223,8 +223,10 @@ def main():
                     help="t* of the gradient leg (a multiple of dt = 0.1; the cost ratio barely depends on it)")
     ap.add_argument("--no-n60", action="store_true", help="skip the N=60 leg (dim 2^30)")
     ap.add_argument("--profile-apply", type=int, default=0,
-                    help="only run this many complex128 apply_H calls and one 1 GiB device copy "
+                    help="only run this many apply_H calls and one 1 GiB device copy "
                          "(for hardware-counter runs), then exit")
+    ap.add_argument("--profile-dtype", choices=("c128", "c64"), default="c128",
+                    help="state precision of the --profile-apply calls")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -250,16 +252,18 @@ def main():
 
     psi = torch.from_numpy(psi_host).to(dev)
     if args.profile_apply > 0:
-        out = torch.empty_like(psi)
+        x = psi if args.profile_dtype == "c128" else psi.to(torch.complex64)
+        out = torch.empty_like(x)
         for k in range(args.profile_apply):
-            api.apply_H(T, psi, out)
+            api.apply_H(T, x, out)
             torch.cuda.synchronize()
             log(f"[bench] apply {k + 1}/{args.profile_apply} done")
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_apply": args.profile_apply, "N": N, "copy_bytes": 1 << 30}), flush=True)
+        print(json.dumps({"profile_apply": args.profile_apply, "dtype": args.profile_dtype, "N": N,
+                          "copy_bytes": 1 << 30}), flush=True)
         return
     log(f"[bench] complex128: {args.warmup} warmup + {args.steps} timed steps (m={m}, dt={dt})")
     wall, n_apply, apply_ms = timed_leg(api, torch, T, psi, args.steps, args.warmup, m, dt)
