@@ -32,8 +32,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # Vector-ALU roofs of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x
-# 2.4 GHz = 78.6 TFLOP/s in FP64; FP32 doubles that only with packed FP32
-# instructions, which this build does not emit.
+# 2.4 GHz = 78.6 TFLOP/s in FP64 and twice that in FP32 (157.3 TFLOP/s), the
+# roof the complex64 leg is measured against.
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 # Arithmetic per (row, flip mask) pair of the grouped product: one complex
