@@ -87,6 +87,17 @@ __device__ __forceinline__ void group_sum(double& a, double& b, uint32_t keep)
     group_stage<5>(a, b, keep);
 }
 
+// The value of the lane that differs from this lane in lane bit B (0 or 1):
+// a DPP quad permutation, both ways.
+template <int B>
+__device__ __forceinline__ double lane_xor(double v)
+{
+    constexpr int ctrl = B == 0 ? 0xb1 : 0x4e;   // quad_perm:[1,0,3,2] / [2,3,0,1]
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
 // The lane of a group_sum group that holds the sum: its bits 0..3 outside keep
 // are set, its bits 4 and 5 outside keep clear.
 __device__ __forceinline__ bool group_rep(uint32_t lane, uint32_t keep)
@@ -309,19 +320,53 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
                                     b = fma(-gi, x.re, b);
                                 }
                             }
-                            const bool rep = group_rep(tid & 63u, keep);   // one lane per bin and wave
-#pragma unroll
-                            for (int pp = 0; pp < RPT; ++pp) {
-                                if ((pp & ~(int)XK) != 0) continue;
-                                double ar = flip31(er[pp], sl), ai = flip31(ei[pp], sl);
-                                group_sum(ar, ai, keep);
+                            // entry pp (a subset of XK) goes to bin il + the index bits its k bits set
+                            auto entry_idx = [&](int pp) {
                                 uint32_t idx = il;
 #pragma unroll
                                 for (int b = 0; b < KB; ++b)
                                     if ((pp >> b) & 1) idx += (q.koffs >> (8 * b)) & 0xffu;
-                                if (rep) {
-                                    atomicAdd(&bins[2 * (16 * slot + idx)], ar);
-                                    atomicAdd(&bins[2 * (16 * slot + idx) + 1], ai);
+                                return idx;
+                            };
+                            auto bin_add = [&](uint32_t idx, double ar, double ai) {
+                                atomicAdd(&bins[2 * (16 * slot + idx)], ar);
+                                atomicAdd(&bins[2 * (16 * slot + idx) + 1], ai);
+                            };
+                            // Several entries and in-wave lane bit 0 or 1 outside keep:
+                            // one exchange over that bit first (lanes with the bit clear
+                            // keep the entries without XK's lowest bit, their partners
+                            // those with it), so the remaining sums run on half as many
+                            // values per lane.
+                            constexpr int T0 = (int)(XK & (0u - XK));   // lowest bit of XK (0: one entry)
+                            auto split_sums = [&](auto bc) {
+                                constexpr int B = decltype(bc)::value;
+                                const uint32_t side = (tid >> B) & 1u;
+                                const uint32_t keep2 = keep | (1u << B);
+                                const bool rep2 = group_rep(tid & 63u, keep2);
+#pragma unroll
+                                for (int pp = 0; pp < RPT; ++pp) {
+                                    if ((pp & ~(int)XK) != 0 || (pp & T0) != 0) continue;
+                                    const double a0 = flip31(er[pp], sl), b0 = flip31(ei[pp], sl);
+                                    const double a1 = flip31(er[pp | T0], sl), b1 = flip31(ei[pp | T0], sl);
+                                    double ar = side ? a1 : a0, ai = side ? b1 : b0;
+                                    ar += lane_xor<B>(side ? a0 : a1);
+                                    ai += lane_xor<B>(side ? b0 : b1);
+                                    group_sum(ar, ai, keep2);
+                                    if (rep2) bin_add(side ? entry_idx(pp | T0) : entry_idx(pp), ar, ai);
+                                }
+                            };
+                            if (T0 != 0 && (keep & 1u) == 0u) {
+                                split_sums(std::integral_constant<int, 0>{});
+                            } else if (T0 != 0 && (keep & 2u) == 0u) {
+                                split_sums(std::integral_constant<int, 1>{});
+                            } else {
+                                const bool rep = group_rep(tid & 63u, keep);   // one lane per bin and wave
+#pragma unroll
+                                for (int pp = 0; pp < RPT; ++pp) {
+                                    if ((pp & ~(int)XK) != 0) continue;
+                                    double ar = flip31(er[pp], sl), ai = flip31(ei[pp], sl);
+                                    group_sum(ar, ai, keep);
+                                    if (rep) bin_add(entry_idx(pp), ar, ai);
                                 }
                             }
                         }
