@@ -227,6 +227,9 @@ def main():
                          "(for hardware-counter runs), then exit")
     ap.add_argument("--profile-dtype", choices=("c128", "c64"), default="c128",
                     help="state precision of the --profile-apply calls")
+    ap.add_argument("--profile-bins", type=int, default=0,
+                    help="only run this many derivative-bin calls (32 pairs of seeded random states at the "
+                         "gradient leg's N) and exit (for kernel-trace and counter runs)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -242,6 +245,18 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     dev = torch.device("cuda:0")
+    if args.profile_bins > 0:
+        Nb = args.grad_N
+        Tb = api.Terms(Nb, inputs.couplings(Nb, 0))
+        gen = torch.Generator(device=dev).manual_seed(3)
+        vs = [torch.randn(Tb.dim, dtype=torch.complex128, device=dev, generator=gen) for _ in range(64)]
+        pairs = [(vs[2 * p], vs[2 * p + 1], 1.0) for p in range(32)]
+        for k in range(args.profile_bins):
+            api.coupling_overlaps(Tb, pairs)
+            torch.cuda.synchronize()
+            log(f"[bench] bins call {k + 1}/{args.profile_bins} done")
+        print(json.dumps({"profile_bins": args.profile_bins, "N": Nb, "pairs": 32}), flush=True)
+        return
     N, m, dt = args.N, args.m, args.dt
     log(f"[bench] N={N}: drawing couplings and state")
     J = inputs.couplings(N, 0)
