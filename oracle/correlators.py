@@ -107,6 +107,26 @@ def two_point_beta0(prop, maj, psi, i: int, times):
     return out
 
 
+def two_point_estimator(prop, maj, psi, i: int, beta: float, times):
+    """G(t) = <chi_i(t) chi_i>_beta at any beta (Eq. 2-3) from a typical state
+    (SI "Disorder averaging"), the thermal trace cut symmetrically:
+        G_est(t) = <phi| chi_i(t) chi_i |phi> / <phi|phi>,  phi = rho^{1/2} psi,
+    with chi_i(t) = U^dag chi_i U, so the numerator is <U phi | chi_i U chi_i phi>.
+    Summed over an orthonormal basis the numerator is Tr[rho^{1/2} chi_i(t)
+    chi_i rho^{1/2}] = Tr[chi_i(t) chi_i rho] and the denominator Tr rho.
+    Each time is propagated from scratch.  Returns (G complex, Z = <phi|phi>);
+    G_R = 2 Re G."""
+    phi = prop.imag(psi, beta / 2)
+    Z = float(np.vdot(phi, phi).real)
+    chi_phi = maj(i, phi)
+    out = np.empty(len(times), dtype=np.complex128)
+    for n, t in enumerate(times):
+        a = prop.real(phi, t)                 # U phi
+        b = prop.real(chi_phi, t)             # U chi_i phi
+        out[n] = np.vdot(a, maj(i, b)) / Z
+    return out, Z
+
+
 def two_point_trace(dense_exp, chis, i: int, beta: float, times):
     """Exact <chi_i(t) chi_i>_beta = Tr[chi_i(t) chi_i rho] / Tr rho."""
     rho = dense_exp.matrix(-beta)

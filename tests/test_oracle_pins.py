@@ -254,6 +254,61 @@ def test_two_point_estimator():
     assert abs((Gh - 0.5) / h ** 2 - (-s2 / 16)) < 1e-6
 
 
+@pytest.mark.parametrize("N,beta", [(4, 2.0), (4, 10.0), (8, 2.5), (8, 7.0)])
+def test_two_point_estimator_finite_beta_basis_sum_is_trace(N, beta):
+    """Finite-beta G(t): summed over an orthonormal basis the estimator's
+    numerator gives Tr[chi_i(t) chi_i rho] and its denominator Tr rho (Eq. 2-3
+    read as a normalized trace).  Splitting rho^{1/2} unevenly, propagating
+    the wrong leg or putting chi_i on the wrong side breaks it.  At N = 4 the
+    basis sum also equals the closed form of tests/golden/n4_closed_form.*."""
+    J = inputs.couplings(N, 6) if N > 4 else np.array([0.7])
+    H = jw.dense_H(N, J)
+    E = krylov.DenseExp(H)
+    chis = jw.dense_majoranas(N)
+    ex = correlators.ExactPropagator(E)
+    maj = lambda a, v: jw.majorana_apply(N, a, v)
+    D = H.shape[0]
+    times = [0.0, 0.5, 3.0, 7.25]
+    i = 0 if N == 4 else 3
+    num = np.zeros(len(times), complex)
+    den = 0.0
+    for r in range(D):
+        e = np.zeros(D, complex)
+        e[r] = 1.0
+        G, Z = correlators.two_point_estimator(ex, maj, e, i, beta, times)
+        num += G * Z
+        den += Z
+    ref = correlators.two_point_trace(E, chis, i, beta, times)
+    assert np.abs(num / den - ref).max() < 1e-13
+    if N == 4:
+        rows = [r for r in _golden_n4() if r[0] == 0.7 and r[1] == beta]
+        assert len(rows) == len(times)
+        gold = np.array([r[4] + 1j * r[5] for r in rows])
+        assert np.abs(num / den - gold).max() < 1e-14
+
+
+def test_two_point_estimator_finite_beta_identities():
+    """G_est(0) = 1/2 for any state and beta (chi^2 = 1/2); at beta = 0 the
+    estimator is the beta = 0 one; G_est(t) at beta equals the beta = 0
+    estimator on the normalized state rho^{1/2} psi (the cut is symmetric)."""
+    N = 8
+    J = inputs.couplings(N, 8)
+    E = krylov.DenseExp(jw.dense_H(N, J))
+    ex = correlators.ExactPropagator(E)
+    maj = lambda a, v: jw.majorana_apply(N, a, v)
+    psi = inputs.typical_state(N, 9)
+    times = [0.0, 0.6, 2.2]
+    G, Z = correlators.two_point_estimator(ex, maj, psi, 5, 4.0, times)
+    assert abs(G[0] - 0.5) < 1e-14
+    G0, Z0 = correlators.two_point_estimator(ex, maj, psi, 5, 0.0, times)
+    assert abs(Z0 - 1.0) < 1e-14
+    assert np.abs(G0 - correlators.two_point_beta0(ex, maj, psi, 5, times)).max() < 1e-15
+    phi = E.apply(psi, -2.0)
+    phi /= np.linalg.norm(phi)
+    assert abs(Z - np.linalg.norm(E.apply(psi, -2.0)) ** 2) < 1e-13 * Z
+    assert np.abs(G - correlators.two_point_beta0(ex, maj, phi, 5, times)).max() < 1e-14
+
+
 def test_typicality_loose():
     """Typical-state F approaches the trace (SI "Disorder averaging"); loose."""
     N = 16
