@@ -118,11 +118,10 @@ def test_sector_correlators_vs_exact(N, beta):
         Fur, Fuir, _ = correlators.otoc_u_estimator(ex, maj, psi, 2, 3, beta, times)
         sc = np.abs(Fur + 1j * Fuir).max()
         assert np.abs(Fu[:, 0] - Fur).max() <= 1e-10 * sc and np.abs(Fui[:, 0] - Fuir).max() <= 1e-10 * sc
-        G, _ = api.two_point(T, 1, beta, times, _gpu(u), m=20, dt=0.25, tau_step=0.25, sector=s)
-        rho_half = ex.imag(psi, beta / 2)
-        Gref = np.array([np.vdot(ex.real(rho_half, t), maj(1, ex.real(maj(1, rho_half), t))) for t in times])
-        Gref /= np.vdot(rho_half, rho_half).real
+        G, Zg = api.two_point(T, 1, beta, times, _gpu(u), m=20, dt=0.25, tau_step=0.25, sector=s)
+        Gref, Zgr = correlators.two_point_estimator(ex, maj, psi, 1, beta, times)
         assert np.abs(G[:, 0] - Gref).max() <= 1e-10 * np.abs(Gref).max()
+        assert abs(Zg[0] - Zgr) <= 1e-10 * Zgr
         if beta > 0:
             Gt, _ = api.imag_two_point(T, 5, beta, taus, _gpu(u), m=20, tau_step=0.25, sector=s)
             Gtr, _ = correlators.imag_two_point_estimator(ex, maj, psi, 5, beta, taus)
