@@ -100,14 +100,17 @@ struct Stepper {
             const void* z = (k + 2 <= K) ? G[k + 2] : nullptr;
             rec(out, w, G[k + 1], z, lam, nullptr, (k == 0 ? 1.0 : 2.0) / s.e_h, -1.0, std::conj(op.c[k]), 0.0);
         }
-        std::vector<const void*> gp, vp;
-        std::vector<double> wp;
-        for (int k = 0; k < K; ++k) {
-            gp.push_back(G[k + 1]);
-            vp.push_back(V[k]);
-            wp.push_back((k == 0 ? 1.0 : 2.0) / s.e_h);
+        // the bins add linearly over pairs: at most kGradMaxPairs pairs per call
+        for (int k0 = 0; k0 < K; k0 += kGradMaxPairs) {
+            std::vector<const void*> gp, vp;
+            std::vector<double> wp;
+            for (int k = k0; k < std::min(K, k0 + kGradMaxPairs); ++k) {
+                gp.push_back(G[k + 1]);
+                vp.push_back(V[k]);
+                wp.push_back((k == 0 ? 1.0 : 2.0) / s.e_h);
+            }
+            grad_bins(c.h, gp, vp, wp, bins, c.stream);
         }
-        grad_bins(c.h, gp, vp, wp, bins, c.stream);
     }
 };
 

@@ -199,6 +199,7 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
         const c128* const* __restrict__ gs = C.layout ? gs_rot : gs_nat;
         const c128* const* __restrict__ vs = C.layout ? vs_rot : vs_nat;
         for (uint32_t e = tid; e < 2 * C.bin_count; e += nt) bins[e] = 0.0;
+        __syncthreads();   // every bin is zero before any wave adds into it (far chunks have no later barrier)
         for (uint32_t tile = tg; tile < L.n_tiles; tile += L.tile_groups) {
             const uint32_t base = tile << L.tile_bits;
             if (!C.far) {
@@ -559,9 +560,9 @@ void grad_bins(syk_terms_s& h, const std::vector<const void*>& g, const std::vec
     const TermTables& T = h.host;
     const int npairs = (int)g.size();
     if (npairs == 0) return;
-    require(npairs <= 64 && (int)v.size() == npairs && (int)w.size() == npairs, "gradient: bad pair list");
+    require(npairs <= kGradMaxPairs && (int)v.size() == npairs && (int)w.size() == npairs, "gradient: bad pair list");
     // 1024-row tiles, 256 threads (the kernel's launch bound)
-    const ApplyTuning tune{10, 256, 1};
+    const ApplyTuning tune{10, 1};
     const ApplyPlan P = plan_apply(H.M, 1, SYK_C128, &tune);
     require(P.nt <= 256 && (P.rpt == 1 || P.nt == 256), "gradient: launch shape");
     const bool two = P.two_layouts != 0;

@@ -11,6 +11,7 @@ namespace syk {
 constexpr int kGradBinCap = 1024;   // derivative bins of one chunk held in LDS
 constexpr int kGradAccMasks = 2;    // PAIR / DIAG masks of one chunk, summed over the pairs in registers
 constexpr int kGradPairsPerStage = 2;   // (g, v) pairs whose source tiles are staged together
+constexpr int kGradMaxPairs = 64;        // (g, v) pairs of one grad_bins call
 
 // A chunk of masks whose bins are held in LDS together: members
 // [first, first + count) of the member list, at most kGradAccMasks of them PAIR
