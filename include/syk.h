@@ -93,11 +93,17 @@ syk_status syk_apply_H(syk_terms t, syk_dtype dtype, int nvec, const int32_t* re
 /* Launch shape of apply_H for this handle (used by the autotuner): each
  * workgroup owns 2^tile_bits rows (0 = automatic, else at most 11; capped at
  * the number of qubits) with min(256, 2^tile_bits) threads, each thread up to 8
- * rows.  threads: 0 or 256 (accepted for compatibility; the thread count
- * follows from tile_bits).  xcd_remap = 1 hands each of the 8 XCDs a
- * contiguous range of row tiles, 0 keeps the hardware's round-robin order.
- * Other values give SYK_EINVAL and leave the setting unchanged. */
-syk_status syk_set_apply_tuning(syk_terms t, int tile_bits, int threads, int xcd_remap);
+ * rows.  xcd_remap = 1 hands each of the 8 XCDs a contiguous range of row
+ * tiles, 0 keeps the hardware's round-robin order.  Other values give
+ * SYK_EINVAL and leave the setting unchanged. */
+syk_status syk_set_apply_tuning(syk_terms t, int tile_bits, int xcd_remap);
+
+/* Cap on the device workspace a handle may hold (Krylov basis, estimator
+ * vectors, Chebyshev stacks, checkpoints, rotated-layout copies of the
+ * gradient), in bytes; 0 removes the cap (the default).  A call that would
+ * grow the workspace beyond the cap returns SYK_ENOMEM before allocating and
+ * leaves the handle valid.  Lowering the cap does not free what is held. */
+syk_status syk_set_workspace_limit(syk_terms t, uint64_t bytes);
 
 /* Kernel timing: while enabled, every apply_H call records a HIP event before
  * and after its kernel launches on the call's stream.  syk_timing_read waits

@@ -106,10 +106,14 @@ class Terms:
             pass
 
 
-def set_apply_tuning(terms: Terms, tile_bits: int = 0, threads: int = 0, xcd_remap: int = 1):
+def set_apply_tuning(terms: Terms, tile_bits: int = 0, xcd_remap: int = 1):
     """Launch shape of apply_H for this handle (0 = automatic); see syk_set_apply_tuning."""
-    check(lib().syk_set_apply_tuning(terms.handle, int(tile_bits), int(threads), int(xcd_remap)),
-          "syk_set_apply_tuning")
+    check(lib().syk_set_apply_tuning(terms.handle, int(tile_bits), int(xcd_remap)), "syk_set_apply_tuning")
+
+
+def set_workspace_limit(terms: Terms, nbytes: int):
+    """Cap on the handle's device workspace in bytes (0 = none); see syk_set_workspace_limit."""
+    check(lib().syk_set_workspace_limit(terms.handle, int(nbytes)), "syk_set_workspace_limit")
 
 
 def timing_enable(on: bool = True):

@@ -73,7 +73,7 @@ def time_shape(terms: api.Terms, x: torch.Tensor, y: torch.Tensor, tile_bits: in
     """Average ms of one apply_H call on x (HIP events on the call's stream)
     with this launch shape; the first call (which builds the shape's tables) is
     not timed."""
-    api.set_apply_tuning(terms, tile_bits, 0, xcd_remap)
+    api.set_apply_tuning(terms, tile_bits, xcd_remap)
     api.apply_H(terms, x, y)
     torch.cuda.synchronize()
     api.timing_reset()
@@ -106,7 +106,7 @@ def tune_apply(terms: api.Terms, dtype: torch.dtype = torch.complex128, nvec: in
     if cache and use_cache:
         hit = read_cache(cache).get(key)
         if hit is not None:
-            api.set_apply_tuning(terms, hit["tile_bits"], 0, hit["xcd_remap"])
+            api.set_apply_tuning(terms, hit["tile_bits"], hit["xcd_remap"])
             return hit
     shape = (terms.dim,) if nvec == 1 else (nvec, terms.dim)
     g = torch.Generator(device="cuda").manual_seed(0)
@@ -118,7 +118,7 @@ def tune_apply(terms: api.Terms, dtype: torch.dtype = torch.complex128, nvec: in
     del x, y
     best = dict(pick(timed))
     best["timed"] = timed
-    api.set_apply_tuning(terms, best["tile_bits"], 0, best["xcd_remap"])
+    api.set_apply_tuning(terms, best["tile_bits"], best["xcd_remap"])
     if cache:
         write_cache(cache, key, best)
     return best

@@ -219,18 +219,16 @@ syk_status syk_apply_H_sector(syk_terms t, syk_dtype dtype, int sector, int nvec
     });
 }
 
-syk_status syk_set_apply_tuning(syk_terms t, int tile_bits, int threads, int xcd_remap)
+syk_status syk_set_apply_tuning(syk_terms t, int tile_bits, int xcd_remap)
 {
     return guard([&] {
         check_handle(t);
         require(tile_bits >= 0 && tile_bits <= 11, "tile_bits must be in [0, 11]");
-        require(threads == 0 || threads == 256, "threads must be 0 or 256");
         require(xcd_remap == 0 || xcd_remap == 1, "xcd_remap must be 0 or 1");
         const bool o_tuned = t->tuned;
-        const int o_tb = t->tune_tile_bits, o_nt = t->tune_threads, o_x = t->tune_xcd;
+        const int o_tb = t->tune_tile_bits, o_x = t->tune_xcd;
         t->tuned = true;
         t->tune_tile_bits = tile_bits;
-        t->tune_threads = threads;
         t->tune_xcd = xcd_remap;
         try {
             (void)plan_for(*t, 1, SYK_C128);   // reject shapes that cannot launch
@@ -238,10 +236,17 @@ syk_status syk_set_apply_tuning(syk_terms t, int tile_bits, int threads, int xcd
         } catch (...) {
             t->tuned = o_tuned;
             t->tune_tile_bits = o_tb;
-            t->tune_threads = o_nt;
             t->tune_xcd = o_x;
             throw;
         }
+    });
+}
+
+syk_status syk_set_workspace_limit(syk_terms t, uint64_t bytes)
+{
+    return guard([&] {
+        check_handle(t);
+        t->ws.limit = (size_t)bytes;
     });
 }
 

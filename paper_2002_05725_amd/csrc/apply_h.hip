@@ -15,6 +15,7 @@
 // source tile.  Up to 64 columns per launch.
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <utility>
 
@@ -860,10 +861,15 @@ std::vector<KRec> build_krecs(const std::vector<MaskRec>& masks, const std::vect
 
 namespace {
 
+int apply_tables_key(const ApplyPlan& P, uint32_t esz, int layout)
+{
+    return (((P.tile_bits * 16 + P.lb) * 32 + (int)esz) * 2 + P.two_layouts) * 2 + layout;
+}
+
 const HamiltonianDev::ApplyTables& apply_tables_for(const HamiltonianDev& H, const ApplyPlan& P, uint32_t esz,
                                                     int layout)
 {
-    const int key = (((P.tile_bits * 16 + P.lb) * 32 + (int)esz) * 2 + P.two_layouts) * 2 + layout;
+    const int key = apply_tables_key(P, esz, layout);
     auto it = H.apply_tables.find(key);
     if (it == H.apply_tables.end()) {
         std::vector<QApplyChunk> ch;
@@ -907,8 +913,6 @@ ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune)
     P.lb = std::min(tb, kLaneBits);
     P.nt = 1 << P.lb;
     P.rpt = 1 << (tb - P.lb);
-    if (tune && tune->threads != 0 && tune->threads != (1 << kLaneBits))
-        throw Error(SYK_EINVAL, "apply_H: threads must be 0 or 256");
     P.xcd_remap = tune ? tune->xcd_remap : 1;
     // QUAD masks whose four qubits all lie above the tile would each stream a
     // whole tile from global memory; with at least C(7,4) of them, run the
@@ -917,8 +921,33 @@ ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune)
     return P;
 }
 
+namespace {
+void launch_apply_impl(const HamiltonianDev& H, syk_dtype dtype, int nvec, const int32_t* real_of_col,
+                       const void* psi, void* out, const ApplyPlan& P, hipStream_t s, void* rot_in, void* rot_out,
+                       bool timed);
+}  // namespace
+
 void launch_apply_h(const HamiltonianDev& H, syk_dtype dtype, int nvec, const int32_t* real_of_col,
                     const void* psi, void* out, const ApplyPlan& P, hipStream_t s)
+{
+    const bool two = P.two_layouts != 0;
+    if (two) {
+        const size_t bytes = (size_t)std::min(nvec, kColsPerLaunch) * ((uint64_t)1 << H.M) * elem_bytes(dtype);
+        H.rot_in.ensure(bytes);
+        H.rot_out.ensure(bytes);
+    }
+    ensure_diag(H, s);
+    launch_apply_impl(H, dtype, nvec, real_of_col, psi, out, P, s, two ? H.rot_in.p : nullptr,
+                      two ? H.rot_out.p : nullptr, true);
+}
+
+namespace {
+
+// The launches of one apply_H call; rot_in / rot_out: state-sized buffers of
+// min(nvec, 64) columns for two-layout plans.  Allocates nothing.
+void launch_apply_impl(const HamiltonianDev& H, syk_dtype dtype, int nvec, const int32_t* real_of_col,
+                       const void* psi, void* out, const ApplyPlan& P, hipStream_t s, void* rot_in, void* rot_out,
+                       bool timed)
 {
     const int M = H.M;
     if (P.lb > kLaneBits || (P.rpt > 1 && P.lb != kLaneBits) || P.nt != (1 << P.lb) ||
@@ -929,13 +958,8 @@ void launch_apply_h(const HamiltonianDev& H, syk_dtype dtype, int nvec, const in
     const uint64_t dim = (uint64_t)1 << M;
     const HamiltonianDev::ApplyTables& A = apply_tables_for(H, P, (uint32_t)esz, 0);
     const HamiltonianDev::ApplyTables* B = P.two_layouts ? &apply_tables_for(H, P, (uint32_t)esz, 1) : nullptr;
-    if (B) {
-        const size_t bytes = (size_t)std::min(nvec, kColsPerLaunch) * dim * esz;
-        H.rot_in.ensure(bytes);
-        H.rot_out.ensure(bytes);
-    }
-    ensure_diag(H, s);
-    timing_begin(s);
+    if (B && (!rot_in || !rot_out)) throw Error(SYK_EINVAL, "apply_H: no buffers for the rotated layout");
+    if (timed) timing_begin(s);
     for (int sl = 0; sl < P.slices; ++sl) {
         KLayout L{};
         L.tile_bits = P.tile_bits;
@@ -965,15 +989,17 @@ void launch_apply_h(const HamiltonianDev& H, syk_dtype dtype, int nvec, const in
         };
         if (B) {
             // rows r -> rotate_bits(r): a [2^(M-s)] x [2^s] transpose
-            launch_transpose(dtype, in_c, H.rot_in.p, M - P.tile_bits, P.tile_bits, ncols, dim, false, s);
-            run(*B, H.rot_in.p, H.rot_out.p);
+            launch_transpose(dtype, in_c, rot_in, M - P.tile_bits, P.tile_bits, ncols, dim, false, s);
+            run(*B, rot_in, rot_out);
             run(A, in_c, out_c);
-            launch_transpose(dtype, H.rot_out.p, out_c, P.tile_bits, M - P.tile_bits, ncols, dim, true, s);
+            launch_transpose(dtype, rot_out, out_c, P.tile_bits, M - P.tile_bits, ncols, dim, true, s);
         } else {
             run(A, in_c, out_c);
         }
     }
-    timing_end(s);
+    if (timed) timing_end(s);
 }
+
+}  // namespace
 
 }  // namespace syk

@@ -58,7 +58,6 @@ static_assert(sizeof(QApplyChunk) == 64, "QApplyChunk layout");
 // Optional overrides of the launch shape (autotuner / benchmarks); 0 = default.
 struct ApplyTuning {
     int tile_bits;
-    int threads;
     int xcd_remap;
 };
 
@@ -80,7 +79,7 @@ ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune);
 // syk_set_apply_tuning settings.
 inline ApplyPlan plan_for(const syk_terms_s& h, int M, int nvec, syk_dtype dtype)
 {
-    ApplyTuning t{h.tune_tile_bits, h.tune_threads, h.tune_xcd};
+    ApplyTuning t{h.tune_tile_bits, h.tune_xcd};
     return plan_apply(M, nvec, dtype, h.tuned ? &t : nullptr);
 }
 inline ApplyPlan plan_for(const syk_terms_s& h, int nvec, syk_dtype dtype) { return plan_for(h, h.H.M, nvec, dtype); }
@@ -107,5 +106,6 @@ void launch_transpose(syk_dtype dtype, const void* src, void* dst, int log_h, in
 // out = H psi for nvec columns stored one after another; real_of_col: host array or NULL.
 void launch_apply_h(const HamiltonianDev& H, syk_dtype dtype, int nvec, const int32_t* real_of_col,
                     const void* psi, void* out, const ApplyPlan& P, hipStream_t s);
+
 
 }  // namespace syk

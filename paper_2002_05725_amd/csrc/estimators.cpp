@@ -56,6 +56,9 @@ void two_point(BlockCtx& c, int i, double beta, const double* t, int nt, const v
     }
     if (Z)
         for (int col = 0; col < B; ++col) Z[col] = z[col];
+    if (o.tol > 0)
+        for (double e : st.err)
+            if (e > o.tol) throw Error(SYK_ENOTCONVERGED, "Krylov error estimate above tolerance");
 }
 
 void otoc(BlockCtx& c, int i, int j, double beta, const double* t, int nt, const void* psi0,

@@ -42,13 +42,24 @@ struct HamiltonianDev {
 };
 
 // Named device workspaces, grown on demand and kept until the handle dies.
+// With a cap (limit > 0), growing past it throws SYK_ENOMEM before allocating.
 struct Workspace {
     std::map<std::string, std::unique_ptr<DevBuf>> bufs;
+    size_t limit = 0;
+    size_t total = 0;   // bytes held over all buffers
     void* get(const std::string& name, size_t bytes)
     {
         auto& b = bufs[name];
         if (!b) b.reset(new DevBuf());
-        b->ensure(bytes);
+        if (bytes > b->bytes) {
+            const size_t after = total - b->bytes + bytes;
+            if (limit > 0 && after > limit)
+                throw Error(SYK_ENOMEM, "workspace of " + std::to_string(after) + " bytes exceeds the cap of " +
+                                            std::to_string(limit) + " bytes (" + name + ")");
+            total -= b->bytes;
+            b->ensure(bytes);
+            total += b->bytes;
+        }
         return b->p;
     }
     // bytes already held under `name` (0 if none)
@@ -57,7 +68,11 @@ struct Workspace {
         auto it = bufs.find(name);
         return (it == bufs.end() || !it->second) ? 0 : it->second->bytes;
     }
-    void release_all() { bufs.clear(); }
+    void release_all()
+    {
+        bufs.clear();
+        total = 0;
+    }
 };
 
 }  // namespace syk
@@ -79,7 +94,7 @@ struct syk_terms_s {
     };
     std::unique_ptr<Sector> sectors[2];
     bool tuned = false;             // apply_H launch shape set by syk_set_apply_tuning
-    int tune_tile_bits = 0, tune_threads = 0, tune_xcd = 1;
+    int tune_tile_bits = 0, tune_xcd = 1;
 };
 
 namespace syk {

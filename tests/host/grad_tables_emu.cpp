@@ -78,7 +78,7 @@ int run_case(int N)
     }
 
     // the gradient's launch shape and layouts (as grad_bins sets them up)
-    const ApplyTuning tune{10, 256, 1};
+    const ApplyTuning tune{10, 1};
     const ApplyPlan P = plan_apply(M, 1, SYK_C128, &tune);
     const bool two = P.two_layouts != 0;
     const int tb = P.tile_bits, lb = P.lb, RPT = P.rpt, KB = tb - lb;

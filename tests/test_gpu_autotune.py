@@ -31,7 +31,7 @@ def test_every_candidate_shape_matches_checker(N):
         ref = native.apply_rows(N, J, psi, rows)
     idx = torch.from_numpy(rows).to(DEV)
     for tb, xr in autotune.candidates(N):
-        api.set_apply_tuning(T, tb, 0, xr)
+        api.set_apply_tuning(T, tb, xr)
         for dt, tol in ((torch.complex128, 1e-12), (torch.complex64, 2e-6)):
             print(f"N={N} tile_bits={tb} xcd_remap={xr} {dt}", flush=True)
             y = api.apply_H(T, torch.from_numpy(psi).to(DEV).to(dt))
@@ -50,7 +50,7 @@ def test_tune_installs_fastest_and_caches(tmp_path):
     # the installed shape gives the same product as the default one
     x = torch.from_numpy(np.stack([inputs.typical_state(N, s) for s in range(4)])).to(DEV).to(torch.complex64)
     y_tuned = api.apply_H(T, x).cpu().numpy()
-    api.set_apply_tuning(T, 0, 0, 1)
+    api.set_apply_tuning(T, 0, 1)
     y_def = api.apply_H(T, x).cpu().numpy()
     assert _rel(y_tuned, y_def) <= 2e-6
     # a second call installs the cached entry without timing
