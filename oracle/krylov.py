@@ -17,8 +17,21 @@ import math
 
 import numpy as np
 import scipy.linalg
+from threadpoolctl import threadpool_limits
 
 
+def _one_blas_thread(fn):
+    """Runs fn with numpy's BLAS on one thread: the loops below interleave small
+    products with the C checker's OpenMP matvec, and idle BLAS threads spinning
+    between products would compete with it for the cores."""
+    def wrapped(*args, **kwargs):
+        with threadpool_limits(1, user_api="blas"):
+            return fn(*args, **kwargs)
+    wrapped.__name__, wrapped.__doc__ = fn.__name__, fn.__doc__
+    return wrapped
+
+
+@_one_blas_thread
 def krylov_step(matvec, psi: np.ndarray, z: complex, m: int, breakdown_tol: float = 1e-13):
     """Return (e^{z H} psi, error estimate) from an m-dimensional Krylov space.
 
@@ -64,6 +77,7 @@ def krylov_step(matvec, psi: np.ndarray, z: complex, m: int, breakdown_tol: floa
     return y, err
 
 
+@_one_blas_thread
 def propagate(matvec, psi: np.ndarray, z: complex, total: float, dt: float, m: int):
     """e^{z * total * H} psi in ceil(total/dt) equal Krylov steps."""
     if total == 0.0:
@@ -90,6 +104,7 @@ class DenseExp:
         return (self.evecs * np.exp(z * self.evals)) @ self.evecs.conj().T
 
 
+@_one_blas_thread
 def lanczos_ritz(matvec, psi: np.ndarray, m: int, breakdown_tol: float = 1e-13):
     """Ritz values of H from an m-step Lanczos run started at psi (the same
     projection as krylov_step: orthonormal basis by classical Gram-Schmidt

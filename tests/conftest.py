@@ -1,14 +1,7 @@
 import os
 import sys
 
-import numpy  # noqa: F401  (loads the BLAS library that the limit below applies to)
 import pytest
-from threadpoolctl import threadpool_limits
-
-# The checker's C code parallelises with OpenMP; numpy's BLAS threads, which
-# spin after every small product of the Krylov loops, would compete with it for
-# the same cores (a 40x slowdown of the checker's Lanczos at N = 20).
-threadpool_limits(1, user_api="blas")
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:

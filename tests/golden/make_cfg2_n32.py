@@ -21,14 +21,8 @@ import time
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-import numpy  # noqa: E402,F401  (loads the BLAS library the limit below applies to)
-from threadpoolctl import threadpool_limits  # noqa: E402
-
 from oracle import correlators, native  # noqa: E402
 from paper_2002_05725_amd import inputs  # noqa: E402
-
-# numpy's BLAS threads would compete with the checker's OpenMP matvec
-threadpool_limits(1, user_api="blas")
 
 N, BETA, M, DT, TAU = 32, 10.0, 30, 0.5, 0.625
 TIMES = [0.0, 5.0, 10.0, 15.0]

@@ -8,6 +8,7 @@ import sys
 
 import numpy as np
 import pytest
+import scipy.sparse as sps
 import torch
 
 from oracle import correlators, jw, krylov, native
@@ -261,7 +262,8 @@ def test_lowest_eigenvalues_n20_vs_dense_and_checker():
     psi = inputs.typical_state(N, 1)
     T = api.Terms(N, J)
     theta, res = api.lowest_eigenvalues(T, _gpu(psi), k=12, m=120)
-    H = jw.dense_H(N, J)
+    sp = native.SparseH(N, J)   # the checker's sparse H, made dense
+    H = sps.csr_matrix((sp.vals, sp.cols, sp.row_ptr), shape=(sp.D, sp.D)).toarray()
     th_ref, res_ref = krylov.lanczos_ritz(lambda v: H @ v, psi, 120)
     conv = res_ref[:12] < 1e-9
     assert conv[:4].all()
