@@ -90,6 +90,25 @@ syk_status syk_terms_info(syk_terms t, int* N, int* n_real, int64_t* dim, int64_
 syk_status syk_apply_H(syk_terms t, syk_dtype dtype, int nvec, const int32_t* real_of_col,
                        const void* psi, void* out, hipStream_t stream);
 
+/*
+ * syk_apply_H for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results as syk_apply_H (full space), with no hipMalloc, hipFree
+ * or other allocation.  The buffers of the second, bit-rotated row layout
+ * (psi copied in that layout and its partial output: 2 * min(nvec, 64) * dim
+ * elements) come from a device scratch array of 128 MiB built into the library,
+ * which each device the library runs on holds until the process ends (e.g.
+ * N <= 44 in complex128 or N <= 46 in complex64 for one column; N < 30 needs
+ * none).  Larger requests return SYK_EINVAL.  The handle's per-dtype tables and
+ * the diagonal of H are built by its first syk_apply_H call of that dtype and
+ * block width: without one, SYK_EINVAL.  Every call on a device shares that
+ * device's scratch, so calls that overlap in time on one device (other streams
+ * or other threads) race and give wrong results; nothing in the scratch has to
+ * start at zero.  The handle's device must be the current device.
+ */
+syk_status syk_apply_H_noalloc(syk_terms t, syk_dtype dtype, int nvec, const int32_t* real_of_col,
+                               const void* psi, void* out, hipStream_t stream);
+
 /* Launch shape of apply_H for this handle (used by the autotuner): each
  * workgroup owns 2^tile_bits rows (0 = automatic, else at most 11; capped at
  * the number of qubits) with min(256, 2^tile_bits) threads, each thread up to 8

@@ -153,6 +153,17 @@ def apply_H(terms: Terms, psi: torch.Tensor, out: torch.Tensor | None = None, re
     return out
 
 
+def apply_H_noalloc(terms: Terms, psi: torch.Tensor, out: torch.Tensor, real_of_col=None) -> torch.Tensor:
+    """out = H psi with no device allocation (syk_apply_H_noalloc); out must be given."""
+    _check_state(psi, terms.dim, "psi")
+    _check_state(out, terms.dim, "out")
+    nvec = _nvec(psi)
+    ra, rp = _real_arr(real_of_col, nvec)
+    check(lib().syk_apply_H_noalloc(terms.handle, _dtype_code(psi), nvec, rp, ctypes.c_void_p(psi.data_ptr()),
+                                    ctypes.c_void_p(out.data_ptr()), _stream()), "syk_apply_H_noalloc")
+    return out
+
+
 def apply_majorana(terms: Terms, a: int, psi: torch.Tensor, out: torch.Tensor | None = None,
                    sector: int | None = None) -> torch.Tensor:
     """chi_a psi; with `sector` psi is a state of that sector and the result one of the other."""

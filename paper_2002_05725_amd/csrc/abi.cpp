@@ -210,6 +210,22 @@ syk_status syk_apply_H(syk_terms t, syk_dtype dtype, int nvec, const int32_t* re
     return guard([&] { apply_impl(t, dtype, -1, nvec, real_of_col, psi, out, stream); });
 }
 
+syk_status syk_apply_H_noalloc(syk_terms t, syk_dtype dtype, int nvec, const int32_t* real_of_col, const void* psi,
+                               void* out, hipStream_t stream)
+{
+    return guard([&] {
+        check_handle(t);
+        check_dtype(dtype);
+        check_block(t, nvec, real_of_col);
+        check_ptr(psi, "psi");
+        check_ptr(out, "out");
+        const size_t bytes = ((size_t)1 << t->H.M) * nvec * elem_bytes(dtype);
+        check_no_overlap(psi, out, bytes);
+        const ApplyPlan P = plan_for(*t, t->H.M, nvec, dtype);
+        launch_apply_h_noalloc(t->H, t->device, dtype, nvec, real_of_col, psi, out, P, stream);
+    });
+}
+
 syk_status syk_apply_H_sector(syk_terms t, syk_dtype dtype, int sector, int nvec, const int32_t* real_of_col,
                               const void* psi, void* out, hipStream_t stream)
 {

@@ -927,6 +927,49 @@ void launch_apply_impl(const HamiltonianDev& H, syk_dtype dtype, int nvec, const
                        bool timed);
 }  // namespace
 
+// Scratch of the allocation-free apply (syk_apply_H_noalloc): the rotated
+// copy of psi and the rotated layout's output of one call, side by side.  Each
+// device holds its own copy for the life of the process; host code reaches it
+// only through the address hipGetSymbolAddress returns on that device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+void* noalloc_scratch_ptr(int device)
+{
+    static std::mutex mu;
+    static std::map<int, void*> ptr;   // per device, set once with that device current
+    std::lock_guard<std::mutex> l(mu);
+    auto it = ptr.find(device);
+    if (it != ptr.end()) return it->second;
+    int cur = -1;
+    SYK_HIP(hipGetDevice(&cur));
+    if (cur != device) throw Error(SYK_EINVAL, "apply_H_noalloc: the handle's device is not the current device");
+    void* p = nullptr;
+    SYK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error(SYK_EHIP, "apply_H_noalloc: no device address for the scratch array");
+    ptr.emplace(device, p);
+    return p;
+}
+
+void launch_apply_h_noalloc(const HamiltonianDev& H, int device, syk_dtype dtype, int nvec,
+                            const int32_t* real_of_col, const void* psi, void* out, const ApplyPlan& P,
+                            hipStream_t s)
+{
+    const size_t esz = elem_bytes(dtype);
+    const uint64_t dim = (uint64_t)1 << H.M;
+    const size_t half = (size_t)std::min(nvec, kColsPerLaunch) * dim * esz;
+    if (P.two_layouts && 2 * half > kNoAllocScratchBytes)
+        throw Error(SYK_EINVAL, "apply_H_noalloc: the rotated layout needs " + std::to_string(2 * half) +
+                                    " bytes of scratch, above the maximum of " +
+                                    std::to_string(kNoAllocScratchBytes));
+    // everything the handle builds on first use must exist already
+    auto have = [&](int layout) { return H.apply_tables.count(apply_tables_key(P, (uint32_t)esz, layout)) != 0; };
+    if (!H.diag_ready || !have(0) || (P.two_layouts && !have(1)))
+        throw Error(SYK_EINVAL, "apply_H_noalloc: the handle has no tables for this dtype and block width yet "
+                                "(call syk_apply_H once with them first)");
+    char* sp = P.two_layouts ? static_cast<char*>(noalloc_scratch_ptr(device)) : nullptr;
+    launch_apply_impl(H, dtype, nvec, real_of_col, psi, out, P, s, sp, sp ? sp + half : nullptr, false);
+}
+
 void launch_apply_h(const HamiltonianDev& H, syk_dtype dtype, int nvec, const int32_t* real_of_col,
                     const void* psi, void* out, const ApplyPlan& P, hipStream_t s)
 {

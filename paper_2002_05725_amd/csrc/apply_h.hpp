@@ -107,5 +107,16 @@ void launch_transpose(syk_dtype dtype, const void* src, void* dst, int log_h, in
 void launch_apply_h(const HamiltonianDev& H, syk_dtype dtype, int nvec, const int32_t* real_of_col,
                     const void* psi, void* out, const ApplyPlan& P, hipStream_t s);
 
+// Bytes of the file-scope device scratch of the allocation-free apply.
+constexpr size_t kNoAllocScratchBytes = (size_t)128 << 20;
+
+// launch_apply_h without any allocation: the rotated layout's two buffers come
+// from the scratch array of `device` (the current device), and the handle's
+// tables for this launch shape and its diagonal must exist already (SYK_EINVAL
+// otherwise, as for plans whose buffers exceed kNoAllocScratchBytes).  Calls
+// that overlap on one device race on the scratch.
+void launch_apply_h_noalloc(const HamiltonianDev& H, int device, syk_dtype dtype, int nvec,
+                            const int32_t* real_of_col, const void* psi, void* out, const ApplyPlan& P,
+                            hipStream_t s);
 
 }  // namespace syk
