@@ -6,15 +6,20 @@
 // k_grad_bins: for pairs (g_p, v_p) with weights w_p, accumulates for every flip
 // mask the bins of sum_p w_p conj(g_p[r]) (-1)^{|r & zbase|} v_p[r ^ x] that
 // determine Re <g_p| Q_n v_p> for each coupling n of the mask (terms.hpp).  A
-// workgroup sweeps a fixed set of tiles for one chunk of masks at a time with
-// the chunk's bins in LDS, then writes them to its own slice of a partial
-// buffer; k_bins_reduce adds the slices in a fixed order.
+// workgroup sweeps a fixed set of 512-row tiles for one chunk of masks at a
+// time with the chunk's bins in LDS, then writes them to its own slice of a
+// partial buffer; k_bins_reduce adds the slices in a fixed order.
 //
-// QUAD bins depend on the row only through its bits at the four flipped
-// qubits: the lanes of a wave that agree on those bits are summed with DPP
-// row shifts and permlane swaps first, and one lane per bin adds to LDS.  PAIR
-// and DIAG bins are linear in sum_p w_p conj(g_p[r]) v_p[r ^ x], which each
-// thread sums over the pairs in registers and bins once per tile.
+// The four waves of a workgroup split a chunk's QUAD masks (every fourth of
+// its list to each), and a wave computes its masks over all rows of the tile
+// (64 lanes x 8 rows).  QUAD bins depend on the row only through its bits at
+// the four flipped qubits: the lanes of the wave that agree on those bits are
+// summed with DPP row shifts and permlane swaps, and one lane per bin adds it
+// to the bin, which no other wave touches.  PAIR and DIAG bins are linear in
+// sum_p w_p conj(g_p[r]) v_p[r ^ x], which each thread sums over the pairs for
+// its two rows of the tile; the rows are then laid out in LDS and every bin is
+// formed by fixed threads in a fixed order.  No float atomics: the bins are the
+// same bits on every run.
 #include "grad.hpp"
 
 #include <algorithm>
@@ -147,7 +152,8 @@ __global__ void __launch_bounds__(256) k_cheb_rec(cplx<R>* out, const cplx<R>* _
 }
 
 struct GLayout {
-    int tile_bits;
+    int tile_bits;                        // rows per tile = 2^tile_bits
+    int lane_bits;                        // in-wave lane bits that index rows (6, fewer for tiny states)
     uint32_t n_tiles;
     uint32_t tile_groups, chunk_groups;   // grid = tile_groups x chunk_groups workgroups
     int n_chunks;
@@ -157,8 +163,17 @@ struct GLayout {
     uint64_t n_bins;
 };
 
-template <int RPT>
-__global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec, const GChunk* __restrict__ chunks,
+// Bins of one launch: four waves of 64 lanes; lane l owns rows l + 64 k
+// (k < 2^KB) of every tile of 2^(lane_bits + KB) rows.  Each QUAD member of a
+// chunk belongs to one wave (every fourth member of the chunk's class-sorted
+// list), which computes it over all rows of the tile: its bins are only ever
+// added to by that wave, one lane per bin and instruction, in program order.
+// PAIR and DIAG masks sum sum_p w_p conj(g_p[r]) v_p[r ^ x] per row over the
+// pairs (each row owned by one thread); at the end of a tile the rows are laid
+// out in LDS and every bin is formed by fixed threads in a fixed row order.
+// Nothing depends on timing, so the bins are the same bits on every run.
+template <int KB>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_grad_bins(const KRec* __restrict__ krec, const GChunk* __restrict__ chunks,
                                                     const uint32_t* __restrict__ members,
                                                     const uint32_t* __restrict__ local,
                                                     const GRec* __restrict__ grec,
@@ -169,25 +184,26 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
                                                     const c128* const* __restrict__ vs_rot,
                                                     const double* __restrict__ wts, double* __restrict__ partial)
 {
-    constexpr int KB = ilog2c(RPT);
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    // threads and lane bits: 256 and 8 whenever a thread owns several rows
-    // (compile-time, so that row offsets become immediate LDS offsets)
-    const uint32_t nt = RPT > 1 ? 256u : blockDim.x;
-    const uint32_t lb = RPT > 1 ? 8u : 31u - __clz(nt);
-    const uint32_t absent = 63u & ~(nt - 1u);                          // in-wave lane bits no thread has
-    const uint32_t tile_elems = nt * RPT;
+    constexpr int RPT = 1 << KB;
     constexpr int PP = kGradPairsPerStage;
-    c128* src = reinterpret_cast<c128*>(smem_raw);                  // [PP][tile_elems]
-    double* bins = reinterpret_cast<double*>(src + PP * tile_elems);   // [kGradBinCap][2]
-    uint32_t* fold = reinterpret_cast<uint32_t*>(bins + 2 * kGradBinCap);   // [kChunkMasks + 1]
-    const uint32_t tid = threadIdx.x;
-    // bits 0..3 and 4..7 of tid, one per byte (table-index gather)
+    constexpr int TS = kGradTileRows;                        // LDS rows per staged pair (the largest tile)
+    constexpr int SR = PP > kGradAccMasks ? PP : kGradAccMasks;
+    __shared__ __align__(16) c128 src[SR * TS];           // source rows; the PAIR / DIAG row sums at tile end
+    __shared__ __align__(16) double bins[2 * kGradBinCap];
+    __shared__ uint32_t fold[kChunkMasks + 4];
+    __shared__ __align__(16) double part[2 * 4 * kGradPairOutputs];   // PAIR outputs of four row quarters
+
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    // the same for every lane of the wave: member positions and records stay scalar
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint32_t tile_rows = 1u << L.tile_bits;
+    const bool live = lane < (1u << L.lane_bits);          // lanes above a tiny state own no rows
+    // bits 0..3 and 4..5 of the lane, one per byte (table-index gather)
     uint32_t B0 = 0, B1 = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        B0 |= ((tid >> i) & 1u) << (8 * i);
-        B1 |= ((tid >> (4 + i)) & 1u) << (8 * i);
+        B0 |= ((lane >> i) & 1u) << (8 * i);
+        B1 |= ((lane >> (4 + i)) & 1u) << (8 * i);
     }
     // workgroup (t, s) of the grid: tiles t, t + tile_groups, ...; chunks s, s + chunk_groups, ...
     const uint32_t tg = blockIdx.x % L.tile_groups, sg = blockIdx.x / L.tile_groups;
@@ -198,121 +214,134 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
         // the pair vectors in the chunk's row layout
         const c128* const* __restrict__ gs = C.layout ? gs_rot : gs_nat;
         const c128* const* __restrict__ vs = C.layout ? vs_rot : vs_nat;
-        for (uint32_t e = tid; e < 2 * C.bin_count; e += nt) bins[e] = 0.0;
-        __syncthreads();   // every bin is zero before any wave adds into it (far chunks have no later barrier)
+        for (uint32_t e = tid; e < 2 * C.bin_count; e += 256) bins[e] = 0.0;
+        __syncthreads();   // every bin is zero before any wave adds into it
         for (uint32_t tile = tg; tile < L.n_tiles; tile += L.tile_groups) {
             const uint32_t base = tile << L.tile_bits;
             if (!C.far) {
                 // tile part of each QUAD member's bin index and sign
                 __syncthreads();   // the previous tile's readers of fold are done
-                for (uint32_t j = tid; j < C.n_quad; j += nt) {
+                for (uint32_t j = tid; j < C.n_quad; j += 256) {
                     const KRec m = krec[members[C.first + j]];
                     fold[j] = quad_index(base, m.qpack) | (parity(base & m.zbase) << 4);
                 }
             }
-            // PAIR / DIAG: sum_p w_p conj(g_p[r]) v_p[r ^ x] for the thread's rows
-            double acc_re[kGradAccMasks][RPT], acc_im[kGradAccMasks][RPT];
+            // PAIR / DIAG: sum_p w_p conj(g_p[r]) v_p[r ^ x] on the rows tid and tid + 256 of the tile
+            double acc_re[kGradAccMasks][2], acc_im[kGradAccMasks][2];
 #pragma unroll
             for (int j = 0; j < kGradAccMasks; ++j)
 #pragma unroll
-                for (int k = 0; k < RPT; ++k) acc_re[j][k] = acc_im[j][k] = 0.0;
+                for (int h = 0; h < 2; ++h) acc_re[j][h] = acc_im[j][h] = 0.0;
 
             // PP pairs at a time (the host pads the list with zero-weight pairs)
             for (int p0 = 0; p0 < L.npairs; p0 += PP) {
-                c128 gk[PP][RPT];   // w_p g_p on the thread's rows
+                c128 gk[PP][RPT];   // w_p g_p on the lane's rows (every wave loads all rows)
 #pragma unroll
                 for (int u = 0; u < PP; ++u) {
-                    const c128* __restrict__ g = gs[p0 + u];
+                    const c128* __restrict__ g = gs[p0 + u] + (base + lane);
                     const double wt = wts[p0 + u];
 #pragma unroll
                     for (int k = 0; k < RPT; ++k) {
-                        gk[u][k] = g[base + tid + k * nt];
-                        gk[u][k].re *= wt;
-                        gk[u][k].im *= wt;
+                        c128 x{0.0, 0.0};
+                        if (live) x = g[64 * k];
+                        gk[u][k].re = x.re * wt;
+                        gk[u][k].im = x.im * wt;
                     }
                 }
                 if (!C.far) {
+                    // the chunk's source tile; rows past a tiny state are zeros
                     __syncthreads();   // previous users of src are done
                     const uint64_t sbase = (uint64_t)(tile ^ C.x_high) << L.tile_bits;
 #pragma unroll
                     for (int u = 0; u < PP; ++u) {
                         const c128* __restrict__ v = vs[p0 + u];
 #pragma unroll
-                        for (int k = 0; k < RPT; ++k) src[u * tile_elems + tid + k * nt] = v[sbase + tid + k * nt];
+                        for (int e = (int)tid; e < TS; e += 256) {
+                            c128 x{0.0, 0.0};
+                            if ((uint32_t)e < tile_rows) x = v[sbase + (uint32_t)e];
+                            src[u * TS + e] = x;
+                        }
                     }
                     __syncthreads();
                 }
-                // sum over the staged pairs of w_p conj(g_p) x_p for source row k of a mask:
-                // the staged tiles, or (far chunks) the mask's own tile
-                auto product = [&](const KRec& m, int k, double& pr, double& pi) {
-                    pr = pi = 0.0;
-#pragma unroll
-                    for (int u = 0; u < PP; ++u) {
-                        const c128 x = C.far ? vs[p0 + u][((uint64_t)(tile ^ m.x_high) << L.tile_bits) + tid + k * nt]
-                                             : src[u * tile_elems + ((tid + k * nt) ^ m.xl)];
-                        pr += gk[u][k].re * x.re + gk[u][k].im * x.im;
-                        pi += gk[u][k].re * x.im - gk[u][k].im * x.re;
-                    }
-                };
 
                 if (C.far) {
-                    // far QUAD masks: every row of the tile has the same bin and sign
-                    for (uint32_t j = C.first; j < C.first + C.count; ++j) {
+                    // far QUAD masks (no row bit of the tile flipped or in the sign): one bin
+                    // per tile; every fourth member of the chunk to this wave
+                    for (uint32_t j = C.first + wave; j < C.first + C.count; j += 4) {
                         const KRec m = krec[members[j]];
                         if ((m.meta >> 28) != MASK_QUAD) continue;
+                        const uint64_t sb = (uint64_t)(tile ^ m.x_high) << L.tile_bits;
                         double ar = 0.0, ai = 0.0;
 #pragma unroll
-                        for (int k = 0; k < RPT; ++k) {
-                            double pr, pi;
-                            product(m, k, pr, pi);
-                            ar += pr;
-                            ai += pi;
+                        for (int u = 0; u < PP; ++u) {
+                            const c128* __restrict__ v = vs[p0 + u];
+#pragma unroll
+                            for (int k = 0; k < RPT; ++k) {
+                                c128 x{0.0, 0.0};
+                                if (live) x = v[sb + lane + 64u * k];
+                                ar = fma(gk[u][k].re, x.re, ar);
+                                ar = fma(gk[u][k].im, x.im, ar);
+                                ai = fma(gk[u][k].re, x.im, ai);
+                                ai = fma(-gk[u][k].im, x.re, ai);
+                            }
                         }
                         const uint32_t s = parity(base & m.zbase);
                         ar = flip(ar, s);
                         ai = flip(ai, s);
-                        group_sum(ar, ai, absent);
-                        if (group_rep(tid & 63u, absent)) {
-                            double* mb = bins + 2 * local[j];
-                            const uint32_t idx = quad_index(base, m.qpack);
-                            atomicAdd(&mb[2 * idx], ar);
-                            atomicAdd(&mb[2 * idx + 1], ai);
+                        group_sum(ar, ai, 0u);
+                        if (group_rep(lane, 0u)) {
+                            double* mb = bins + 2 * (local[j] + quad_index(base, m.qpack));
+                            mb[0] += ar;
+                            mb[1] += ai;
                         }
                     }
                 } else {
-                    // near QUAD members, class by class
-                    uint32_t j = C.first;
-                    // the next member's record and fold, loaded one member ahead (both lists run one past the end)
-                    GRec qn = grec[j];
-                    uint32_t fon = fold[0];
+                    // near QUAD members, class by class: positions wave, wave + 4, ... of the
+                    // class-sorted list (the next one's record and fold loaded ahead; both
+                    // lists run four past the end)
+                    uint32_t pos = wave, cls_end = 0;
+                    GRec qn = grec[C.first + pos];
+                    uint32_t fon = fold[pos];
                     auto class_loop = [&](auto cls) {
                         constexpr int CL = decltype(cls)::value;
                         constexpr uint32_t XK = (uint32_t)class_bits(CL, KB, 1);   // k bits the masks flip
                         constexpr uint32_t ZK = (uint32_t)class_bits(CL, KB, 2);   // k bits in their Z string
-                        const uint32_t n = (C.cnt[CL >> 2] >> (8 * (CL & 3))) & 0xffu;
-                        for (uint32_t i = 0; i < n; ++i, ++j) {
+                        cls_end += (C.cnt[CL >> 2] >> (8 * (CL & 3))) & 0xffu;
+                        for (; pos < cls_end; pos += 4) {
                             const GRec q = qn;
-                            const uint32_t slot = j - C.first;
+                            const uint32_t slot = pos;
                             const uint32_t fo = fon;
-                            qn = grec[j + 1];
-                            fon = fold[slot + 1];
+                            qn = grec[C.first + pos + 4];
+                            fon = fold[pos + 4];
                             const uint32_t il = __builtin_amdgcn_udot4(__builtin_amdgcn_perm(B1, B0, q.sel), 0x08040201u,
                                                                        fo & 15u, false);
-                            const uint32_t sl = ((uint32_t)__popc(tid & q.zl) ^ (fo >> 4)) << 31;
-                            const uint32_t keep = (q.koffs >> 24) | absent;
+                            const uint32_t sl = (((uint32_t)__popc(lane & q.zl) ^ (fo >> 4)) & 1u) << 31;
+                            const uint32_t keep = q.koffs >> 24;
                             double er[RPT], ei[RPT];   // by the flipped k bits p = k & XK
 #pragma unroll
                             for (int pp = 0; pp < RPT; ++pp) er[pp] = ei[pp] = 0.0;
-                            const uint32_t sb = tid ^ q.xoff;
+                            const uint32_t sb = lane ^ q.xoff;
+                            // source rows of row k (both pairs), read kAhead rows before their FMAs
+                            constexpr int kAhead = 2;
+                            c128 xs[kAhead + 1][PP];
+                            auto read_row = [&](int k, c128 (&x)[PP]) {
+#pragma unroll
+                                for (int u = 0; u < PP; ++u) x[u] = src[u * TS + sb + (((uint32_t)k ^ XK) << 6)];
+                            };
+#pragma unroll
+                            for (int k = 0; k < kAhead && k < RPT; ++k) read_row(k, xs[k]);
 #pragma unroll
                             for (int k = 0; k < RPT; ++k) {
+                                if (k + kAhead < RPT) read_row(k + kAhead, xs[(k + kAhead) % (kAhead + 1)]);
+                                __builtin_amdgcn_sched_barrier(0);
                                 // += (sign of row k) conj(w g) x, straight into the entry's sums
                                 const bool neg = (__builtin_popcount((uint32_t)k & ZK) & 1) != 0;
                                 double& a = er[k & (int)XK];
                                 double& b = ei[k & (int)XK];
 #pragma unroll
                                 for (int u = 0; u < PP; ++u) {
-                                    const c128 x = src[u * tile_elems + sb + (((uint32_t)k ^ XK) << lb)];
+                                    const c128 x = xs[k % (kAhead + 1)][u];
                                     const double gr = neg ? -gk[u][k].re : gk[u][k].re;
                                     const double gi = neg ? -gk[u][k].im : gk[u][k].im;
                                     a = fma(gr, x.re, a);
@@ -320,6 +349,7 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
                                     b = fma(gr, x.im, b);
                                     b = fma(-gi, x.re, b);
                                 }
+                                __builtin_amdgcn_sched_barrier(0);
                             }
                             // entry pp (a subset of XK) goes to bin il + the index bits its k bits set
                             auto entry_idx = [&](int pp) {
@@ -329,9 +359,11 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
                                     if ((pp >> b) & 1) idx += (q.koffs >> (8 * b)) & 0xffu;
                                 return idx;
                             };
+                            // this wave is the only one that adds into the member's bins
                             auto bin_add = [&](uint32_t idx, double ar, double ai) {
-                                atomicAdd(&bins[2 * (16 * slot + idx)], ar);
-                                atomicAdd(&bins[2 * (16 * slot + idx) + 1], ai);
+                                double* mb = bins + 2 * (16 * slot + idx);
+                                mb[0] += ar;
+                                mb[1] += ai;
                             };
                             // Several entries and in-wave lane bit 0 or 1 outside keep:
                             // one exchange over that bit first (lanes with the bit clear
@@ -341,9 +373,9 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
                             constexpr int T0 = (int)(XK & (0u - XK));   // lowest bit of XK (0: one entry)
                             auto split_sums = [&](auto bc) {
                                 constexpr int B = decltype(bc)::value;
-                                const uint32_t side = (tid >> B) & 1u;
+                                const uint32_t side = (lane >> B) & 1u;
                                 const uint32_t keep2 = keep | (1u << B);
-                                const bool rep2 = group_rep(tid & 63u, keep2);
+                                const bool rep2 = group_rep(lane, keep2);
 #pragma unroll
                                 for (int pp = 0; pp < RPT; ++pp) {
                                     if ((pp & ~(int)XK) != 0 || (pp & T0) != 0) continue;
@@ -361,7 +393,7 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
                             } else if (T0 != 0 && (keep & 2u) == 0u) {
                                 split_sums(std::integral_constant<int, 1>{});
                             } else {
-                                const bool rep = group_rep(tid & 63u, keep);   // one lane per bin and wave
+                                const bool rep = group_rep(lane, keep);   // one lane per bin
 #pragma unroll
                                 for (int pp = 0; pp < RPT; ++pp) {
                                     if ((pp & ~(int)XK) != 0) continue;
@@ -374,51 +406,108 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
                     };
                     for_each_class(class_loop, std::make_integer_sequence<int, ipow3(KB)>{});
                 }
+                // PAIR / DIAG rows of this thread, tid and tid + 256 of the tile: the
+                // lane's rows k = wave and wave + 4 (w_p g_p already in gk)
 #pragma unroll
                 for (int j = 0; j < kGradAccMasks; ++j) {
                     if (j >= (int)C.n_acc) break;
                     const KRec ma = krec[members[C.first + C.acc[j]]];
 #pragma unroll
                     for (int k = 0; k < RPT; ++k) {
-                        double pr, pi;
-                        product(ma, k, pr, pi);
-                        acc_re[j][k] += pr;
-                        acc_im[j][k] += pi;
+                        if ((uint32_t)(k & 3) != wave || !live) continue;
+                        const uint32_t rl = lane + 64u * (uint32_t)k;
+                        double& ar = acc_re[j][k >> 2];
+                        double& ai = acc_im[j][k >> 2];
+#pragma unroll
+                        for (int u = 0; u < PP; ++u) {
+                            const c128 x = C.far ? vs[p0 + u][((uint64_t)(tile ^ ma.x_high) << L.tile_bits) + rl]
+                                                 : src[u * TS + (rl ^ ma.xl)];
+                            ar = fma(gk[u][k].re, x.re, fma(gk[u][k].im, x.im, ar));
+                            ai = fma(gk[u][k].re, x.im, fma(-gk[u][k].im, x.re, ai));
+                        }
                     }
                 }
             }
 
-            // bins of the PAIR / DIAG masks from the pair sums of this tile
+            // bins of the PAIR / DIAG masks from this tile's row sums
+            if (C.n_acc > 0) {
+                __syncthreads();   // every wave is done with src
+                c128* rows = src;   // [kGradAccMasks][TS]
 #pragma unroll
-            for (int j = 0; j < kGradAccMasks; ++j) {
-                if (j >= (int)C.n_acc) break;
-                const KRec m = krec[members[C.first + C.acc[j]]];
-                double* mb = bins + 2 * local[C.first + C.acc[j]];
-                if ((m.meta >> 28) == MASK_PAIR) {
-                    const uint32_t q0 = mask_q(m.qpack, 0), q1 = mask_q(m.qpack, 1);
+                for (int j = 0; j < kGradAccMasks; ++j) {
+                    if (j >= (int)C.n_acc) break;
 #pragma unroll
-                    for (int k = 0; k < RPT; ++k) {
-                        const uint32_t r = base | tid | (k * nt);
-                        const uint32_t s = parity(r & m.zbase);
-                        const double pr = flip(acc_re[j][k], s);
-                        const double pi = flip(acc_im[j][k], s);
-                        const uint32_t idx = bit(r, q0) | (bit(r, q1) << 1);
-                        atomicAdd(&mb[2 * idx], pr);
-                        atomicAdd(&mb[2 * idx + 1], pi);
-                        for (uint32_t rb = r & ((1u << L.M) - 1u); rb; rb &= rb - 1) {
-                            const uint32_t c = __ffs(rb) - 1;
-                            atomicAdd(&mb[2 * (4 + 4 * c + idx)], pr);
-                            atomicAdd(&mb[2 * (4 + 4 * c + idx) + 1], pi);
-                        }
+                    for (int h = 0; h < 2; ++h) {
+                        const uint32_t rl = tid + 256u * h;
+                        if (rl < tile_rows) rows[j * TS + rl] = c128{acc_re[j][h], acc_im[j][h]};
                     }
-                } else {  // MASK_DIAG
+                }
+                __syncthreads();
 #pragma unroll
-                    for (int k = 0; k < RPT; ++k) {
-                        const uint32_t r = base | tid | (k * nt);
-                        for (int n = 0; n < L.n_diag; ++n) {
-                            const uint32_t s = parity(r & dz[n]);
-                            atomicAdd(&mb[2 * n], flip(acc_re[j][k], s));
-                            atomicAdd(&mb[2 * n + 1], flip(acc_im[j][k], s));
+                for (int j = 0; j < kGradAccMasks; ++j) {
+                    if (j >= (int)C.n_acc) break;
+                    const KRec m = krec[members[C.first + C.acc[j]]];
+                    double* mb = bins + 2 * local[C.first + C.acc[j]];
+                    const c128* rj = rows + j * TS;
+                    if ((m.meta >> 28) == MASK_PAIR) {
+                        // output o: rows with bits idx = o & 3 at (q0, q1), and for o >= 4 also
+                        // bit c = (o >> 2) - 1 of the tile row set; four threads per output sum
+                        // a quarter of the rows each, then one thread adds the quarters in order
+                        const uint32_t q0 = mask_q(m.qpack, 0), q1 = mask_q(m.qpack, 1);
+                        const uint32_t nout = 4u * (uint32_t)(L.tile_bits + 1);
+                        if (tid < 4 * nout) {
+                            const uint32_t o = tid >> 2, qtr = tid & 3u, idx = o & 3u;
+                            const int c = (int)(o >> 2) - 1;
+                            const uint32_t n4 = tile_rows >> 2;
+                            double sr = 0.0, si = 0.0;
+                            for (uint32_t rl = qtr * n4; rl < (qtr + 1) * n4; ++rl) {
+                                const uint32_t r = base | rl;
+                                if ((bit(r, q0) | (bit(r, q1) << 1)) != idx) continue;
+                                if (c >= 0 && !bit(rl, (uint32_t)c)) continue;
+                                const c128 v = rj[rl];
+                                const uint32_t s = parity(r & m.zbase);
+                                sr += flip(v.re, s);
+                                si += flip(v.im, s);
+                            }
+                            part[2 * tid] = sr;
+                            part[2 * tid + 1] = si;
+                        }
+                        __syncthreads();
+                        if (tid < nout) {
+                            const uint32_t o = tid, idx = o & 3u;
+                            const int c = (int)(o >> 2) - 1;
+                            double sr = 0.0, si = 0.0;
+#pragma unroll
+                            for (int qtr = 0; qtr < 4; ++qtr) {
+                                sr += part[2 * (4 * o + qtr)];
+                                si += part[2 * (4 * o + qtr) + 1];
+                            }
+                            if (c >= 0) {
+                                mb[2 * (4 + 4 * c + idx)] += sr;
+                                mb[2 * (4 + 4 * c + idx) + 1] += si;
+                            } else {
+                                mb[2 * idx] += sr;
+                                mb[2 * idx + 1] += si;
+                                // tile bits of the row: the same for every row of the tile
+                                for (int cq = L.tile_bits; cq < L.M; ++cq)
+                                    if (bit(base, (uint32_t)cq)) {
+                                        mb[2 * (4 + 4 * cq + idx)] += sr;
+                                        mb[2 * (4 + 4 * cq + idx) + 1] += si;
+                                    }
+                            }
+                        }
+                        __syncthreads();   // part is free for the next mask
+                    } else {   // MASK_DIAG: one thread per diagonal term, all rows in order
+                        for (int n = (int)tid; n < L.n_diag; n += 256) {
+                            double sr = 0.0, si = 0.0;
+                            for (uint32_t rl = 0; rl < tile_rows; ++rl) {
+                                const c128 v = rj[rl];
+                                const uint32_t s = parity((base | rl) & dz[n]);
+                                sr += flip(v.re, s);
+                                si += flip(v.im, s);
+                            }
+                            mb[2 * n] += sr;
+                            mb[2 * n + 1] += si;
                         }
                     }
                 }
@@ -430,7 +519,7 @@ __global__ void __launch_bounds__(256) k_grad_bins(const KRec* __restrict__ krec
             const uint32_t lo = local[j];
             const uint32_t hi = (j + 1 < C.first + C.count) ? local[j + 1] : C.bin_count;
             const uint64_t go = krec[members[j]].bin0;
-            for (uint32_t e = tid; e < 2 * (hi - lo); e += nt) mine[2 * go + e] = bins[2 * lo + e];
+            for (uint32_t e = tid; e < 2 * (hi - lo); e += 256) mine[2 * go + e] = bins[2 * lo + e];
         }
         __syncthreads();
     }
@@ -533,7 +622,8 @@ GradChunks make_grad_chunks(const std::vector<MaskRec>& masks, const std::vector
         }
         g.chunks.push_back(b.c);
     }
-    g.grec.push_back(GRec{});   // one record past the end: the kernel loads one member ahead
+    // records past the end: a wave loads its next member's record four positions ahead
+    for (int k = 0; k < kGradRecPad; ++k) g.grec.push_back(GRec{});
     return g;
 }
 
@@ -561,45 +651,50 @@ void grad_bins(syk_terms_s& h, const std::vector<const void*>& g, const std::vec
     const int npairs = (int)g.size();
     if (npairs == 0) return;
     require(npairs <= kGradMaxPairs && (int)v.size() == npairs && (int)w.size() == npairs, "gradient: bad pair list");
-    // 1024-row tiles, 256 threads (the kernel's launch bound)
-    const ApplyTuning tune{10, 1};
-    const ApplyPlan P = plan_apply(H.M, 1, SYK_C128, &tune);
-    require(P.nt <= 256 && (P.rpt == 1 || P.nt == 256), "gradient: launch shape");
-    const bool two = P.two_layouts != 0;
+    // tiles of 512 rows (64 lanes x 8 rows per wave), fewer for small states
+    const int M = H.M;
+    const int tb = std::min(kGradTileBits, M);
+    const int lb = std::min(tb, 6);
+    const int kb = tb - lb;
+    // QUAD masks whose four qubits lie above the tile would each stream a whole
+    // tile; with at least C(7,4) of them, run those that sit better in the
+    // bit-rotated row layout there (as apply_H does)
+    const bool two = M - tb >= 7 && tb >= 8;
     // mask records, chunk records, member list, LDS bin offsets and QUAD member
     // records in one device buffer
-    const int key = P.tile_bits * 2 + (two ? 1 : 0);
+    const int key = tb * 2 + (two ? 1 : 0);
     auto it = h.grad_chunks.find(key);
     if (it == h.grad_chunks.end()) {
         std::vector<MaskRec> lm(T.masks);
         std::vector<uint8_t> lay(T.masks.size(), 0);
         if (two)
             for (size_t i = 0; i < lm.size(); ++i)
-                if (quad_in_rotated(T.masks[i], H.M, P.tile_bits)) {
-                    lm[i] = rotate_mask(T.masks[i], H.M, P.tile_bits);
+                if (quad_in_rotated(T.masks[i], M, tb)) {
+                    lm[i] = rotate_mask(T.masks[i], M, tb);
                     lay[i] = 1;
                 }
-        const std::vector<KRec> kr = build_krecs(lm, T.bin_off, P.tile_bits);
-        const GradChunks c = make_grad_chunks(lm, lay, T.bin_off, T.n_bins, P.tile_bits, P.lb);
-        const size_t kb = kr.size() * sizeof(KRec), cb = c.chunks.size() * sizeof(GChunk);
+        const std::vector<KRec> kr = build_krecs(lm, T.bin_off, tb);
+        const GradChunks c = make_grad_chunks(lm, lay, T.bin_off, T.n_bins, tb, lb);
+        const size_t kbytes = kr.size() * sizeof(KRec), cb = c.chunks.size() * sizeof(GChunk);
         const size_t gb = c.grec.size() * sizeof(GRec), mb = c.members.size() * sizeof(uint32_t);
         std::unique_ptr<DevBuf> b(new DevBuf());
-        b->ensure(kb + cb + gb + 2 * mb);
+        b->ensure(kbytes + cb + gb + 2 * mb);
         char* d = static_cast<char*>(b->p);
-        SYK_HIP(hipMemcpy(d, kr.data(), kb, hipMemcpyHostToDevice));
-        SYK_HIP(hipMemcpy(d + kb, c.chunks.data(), cb, hipMemcpyHostToDevice));
-        SYK_HIP(hipMemcpy(d + kb + cb, c.grec.data(), gb, hipMemcpyHostToDevice));
-        SYK_HIP(hipMemcpy(d + kb + cb + gb, c.members.data(), mb, hipMemcpyHostToDevice));
-        SYK_HIP(hipMemcpy(d + kb + cb + gb + mb, c.local.data(), mb, hipMemcpyHostToDevice));
+        SYK_HIP(hipMemcpy(d, kr.data(), kbytes, hipMemcpyHostToDevice));
+        SYK_HIP(hipMemcpy(d + kbytes, c.chunks.data(), cb, hipMemcpyHostToDevice));
+        SYK_HIP(hipMemcpy(d + kbytes + cb, c.grec.data(), gb, hipMemcpyHostToDevice));
+        SYK_HIP(hipMemcpy(d + kbytes + cb + gb, c.members.data(), mb, hipMemcpyHostToDevice));
+        SYK_HIP(hipMemcpy(d + kbytes + cb + gb + mb, c.local.data(), mb, hipMemcpyHostToDevice));
         h.grad_nchunks[key] = (int)c.chunks.size();
         h.grad_nmembers[key] = (int)c.members.size();
         it = h.grad_chunks.emplace(key, std::move(b)).first;
     }
     GLayout L{};
-    L.tile_bits = P.tile_bits;
-    L.n_tiles = (uint32_t)(((uint64_t)1 << H.M) >> P.tile_bits);
+    L.tile_bits = tb;
+    L.lane_bits = lb;
+    L.n_tiles = (uint32_t)(((uint64_t)1 << M) >> tb);
     L.n_chunks = h.grad_nchunks[key];
-    L.M = H.M;
+    L.M = M;
     L.n_diag = H.n_diag;
     L.n_bins = T.n_bins;
     // tile groups own the partial slices; chunk groups split each tile's
@@ -609,7 +704,7 @@ void grad_bins(syk_terms_s& h, const std::vector<const void*>& g, const std::vec
     L.chunk_groups = (uint32_t)std::max(1, std::min(L.n_chunks, 2048 / nblk));
 
     // rotated copies of the pair vectors for the masks of the second layout
-    const uint64_t dim = (uint64_t)1 << H.M;
+    const uint64_t dim = (uint64_t)1 << M;
     std::vector<const void*> gr(npairs), vr(npairs);
     for (int p = 0; p < npairs; ++p) {
         gr[p] = g[p];
@@ -617,8 +712,8 @@ void grad_bins(syk_terms_s& h, const std::vector<const void*>& g, const std::vec
         if (!two) continue;
         void* a = h.ws.get("grad_rot_g" + std::to_string(p), dim * sizeof(c128));
         void* b = h.ws.get("grad_rot_v" + std::to_string(p), dim * sizeof(c128));
-        launch_transpose(SYK_C128, g[p], a, H.M - P.tile_bits, P.tile_bits, 1, dim, false, st);
-        launch_transpose(SYK_C128, v[p], b, H.M - P.tile_bits, P.tile_bits, 1, dim, false, st);
+        launch_transpose(SYK_C128, g[p], a, M - tb, tb, 1, dim, false, st);
+        launch_transpose(SYK_C128, v[p], b, M - tb, tb, 1, dim, false, st);
         gr[p] = a;
         vr[p] = b;
     }
@@ -648,19 +743,17 @@ void grad_bins(syk_terms_s& h, const std::vector<const void*>& g, const std::vec
     const double* wl = (const double*)(gl + 4 * np);
 
     double* partial = (double*)h.ws.get("grad_partial", (size_t)nblk * T.n_bins * 2 * sizeof(double));
-    const size_t lds = (size_t)kGradPairsPerStage * ((size_t)1 << P.tile_bits) * sizeof(c128) +
-                       (size_t)kGradBinCap * 2 * sizeof(double) + (size_t)(kChunkMasks + 1) * sizeof(uint32_t);
     const KRec* krec = it->second->as<KRec>();
     const GChunk* chunks = reinterpret_cast<const GChunk*>(krec + T.masks.size());
     const GRec* grec = reinterpret_cast<const GRec*>(chunks + L.n_chunks);
-    const uint32_t* members = reinterpret_cast<const uint32_t*>(grec + h.grad_nmembers[key] + 1);
+    const uint32_t* members = reinterpret_cast<const uint32_t*>(grec + h.grad_nmembers[key] + kGradRecPad);
     const uint32_t* local = members + h.grad_nmembers[key];
-    const dim3 grid(nblk * L.chunk_groups), block(P.nt);
-    switch (P.rpt) {
-    case 1: hipLaunchKernelGGL(k_grad_bins<1>, grid, block, lds, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, glr, vlr, wl, partial); break;
-    case 2: hipLaunchKernelGGL(k_grad_bins<2>, grid, block, lds, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, glr, vlr, wl, partial); break;
-    case 4: hipLaunchKernelGGL(k_grad_bins<4>, grid, block, lds, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, glr, vlr, wl, partial); break;
-    case 8: hipLaunchKernelGGL(k_grad_bins<8>, grid, block, lds, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, glr, vlr, wl, partial); break;
+    const dim3 grid(nblk * L.chunk_groups), block(256);
+    switch (kb) {
+    case 0: hipLaunchKernelGGL(k_grad_bins<0>, grid, block, 0, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, glr, vlr, wl, partial); break;
+    case 1: hipLaunchKernelGGL(k_grad_bins<1>, grid, block, 0, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, glr, vlr, wl, partial); break;
+    case 2: hipLaunchKernelGGL(k_grad_bins<2>, grid, block, 0, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, glr, vlr, wl, partial); break;
+    case 3: hipLaunchKernelGGL(k_grad_bins<3>, grid, block, 0, st, krec, chunks, members, local, grec, H.dz, L, gl, vl, glr, vlr, wl, partial); break;
     default: throw Error(SYK_EUNSUPPORTED, "gradient: launch shape");
     }
     SYK_HIP(hipGetLastError());

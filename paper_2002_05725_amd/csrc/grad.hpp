@@ -9,9 +9,12 @@
 namespace syk {
 
 constexpr int kGradBinCap = 1024;   // derivative bins of one chunk held in LDS
-constexpr int kGradAccMasks = 2;    // PAIR / DIAG masks of one chunk, summed over the pairs in registers
+constexpr int kGradAccMasks = 2;    // PAIR / DIAG masks of one chunk, summed over the pairs per row
 constexpr int kGradPairsPerStage = 2;   // (g, v) pairs whose source tiles are staged together
 constexpr int kGradMaxPairs = 64;        // (g, v) pairs of one grad_bins call
+constexpr int kGradTileBits = 9;         // rows of a tile of the bins kernel (fewer for states of fewer rows)
+constexpr int kGradTileRows = 1 << kGradTileBits;
+constexpr int kGradPairOutputs = 4 * (kGradTileBits + 1);   // per-tile sums of a PAIR mask (bins kernel)
 
 // A chunk of masks whose bins are held in LDS together: members
 // [first, first + count) of the member list, at most kGradAccMasks of them PAIR
@@ -37,11 +40,13 @@ struct alignas(16) GRec {
     uint32_t koffs;  // byte b < 3: index bit set by k bit b (0 if not flipped); byte 3: in-wave lane bits of x
 };
 
+constexpr int kGradRecPad = 4;   // zero QUAD member records after the last one
+
 struct GradChunks {
     std::vector<GChunk> chunks;
     std::vector<uint32_t> members;   // mask index of each member
     std::vector<uint32_t> local;     // first LDS bin of each member
-    std::vector<GRec> grec;          // per member (zero for all but near QUAD members), plus one zero record
+    std::vector<GRec> grec;          // per member (zero for all but near QUAD members), plus kGradRecPad zero records
 };
 
 // masks: every mask in mask order, in the coordinates of its layout

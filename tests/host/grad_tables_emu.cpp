@@ -3,19 +3,23 @@
 // Builds the gradient chunk tables with the library's host code
 // (make_grad_chunks, build_krecs, the launch shape and row layouts the
 // gradient uses) and evaluates the bins from them the way k_grad_bins reads
-// them, lane by lane: near chunks (source tile of the chunk, QUAD members by
-// row class with the per-tile fold of index and sign), far chunks (each mask's
-// own source tile) and the PAIR / DIAG sums binned per row.  Two (g, v) pairs
-// with weights are summed.  It also checks what the in-wave lane sums rely on:
-// every lane of a group (lanes that differ only in in-wave bits outside keep)
-// computes the same bin index.  The result is compared with the bins' own
-// definitions in natural row coordinates:
+// them: the waves' shares of a near chunk's class-sorted QUAD members (every
+// fourth position through the classes, each over all rows of the tile, lane
+// by lane with the per-tile fold of index and sign), far chunks (each mask's
+// own source tile), and the PAIR / DIAG row sums turned into bins per tile by
+// the kernel's outputs (four row quarters per PAIR output, tile bits added
+// afterwards; one sum per diagonal term).  Two (g, v) pairs with weights are
+// summed.  It also checks what the kernel relies on: every lane of an in-wave
+// sum group (lanes that differ only in bits outside keep) computes the same
+// bin index, every QUAD member sits in the class its position says and is
+// visited by exactly one wave per tile.  The result is compared with the bins'
+// own definitions in natural row coordinates:
 //   QUAD  B[idx]       = sum_p w_p sum_r conj(g_p[r]) (-1)^{|r & zbase|} v_p[r ^ x], rows with bits idx at q0..q3
 //   PAIR  B[idx], C_c  = the same over rows with bits idx at q0, q1 (C_c: rows with r_c = 1)
 //   DIAG  E_n          = sum_p w_p sum_r conj(g_p[r]) (-1)^{|r & dz_n|} v_p[r]
 //
-// Exit status 0 when every case agrees to 1e-12 relative and no index check
-// failed; one line per case on stdout.
+// Exit status 0 when every case agrees to 1e-12 relative and no check failed;
+// one line per case on stdout.
 #include "grad.hip"
 
 #include <complex>
@@ -78,11 +82,8 @@ int run_case(int N)
     }
 
     // the gradient's launch shape and layouts (as grad_bins sets them up)
-    const ApplyTuning tune{10, 1};
-    const ApplyPlan P = plan_apply(M, 1, SYK_C128, &tune);
-    const bool two = P.two_layouts != 0;
-    const int tb = P.tile_bits, lb = P.lb, RPT = P.rpt, KB = tb - lb;
-    const uint32_t nt = (uint32_t)P.nt;
+    const int tb = std::min(kGradTileBits, M), lb = std::min(tb, 6), KB = tb - lb, RPT = 1 << KB;
+    const bool two = M - tb >= 7 && tb >= 8;
     std::vector<MaskRec> lm(T.masks);
     std::vector<uint8_t> lay(T.masks.size(), 0);
     if (two)
@@ -103,9 +104,8 @@ int run_case(int N)
         }
 
     std::vector<C> out(T.n_bins, 0.0);
-    int index_errors = 0;
-    const uint32_t absent = 63u & ~(nt - 1u);
-    const uint32_t tile_elems = nt * (uint32_t)RPT;
+    int index_errors = 0, visit_errors = 0;
+    const uint32_t tile_rows = 1u << tb;
     for (const GChunk& c : GC.chunks) {
         const std::vector<std::vector<C>>& gs = c.layout ? g_rot : g;
         const std::vector<std::vector<C>>& vs = c.layout ? v_rot : v;
@@ -121,52 +121,55 @@ int run_case(int N)
                     fold[j] = qi | ((uint32_t)(__builtin_popcount(base & m.zbase) & 1) << 4);
                 }
             const uint64_t sbase = (uint64_t)(tile ^ c.x_high) << tb;
-            std::vector<C> acc((size_t)kGradAccMasks * tile_elems, 0.0);
-            for (uint32_t tid = 0; tid < nt; ++tid) {
-                auto gk = [&](int u, int k) { return wt[u] * gs[u][base + tid + (uint32_t)k * nt]; };
-                // sum over the pairs of w conj(g) x for row k, x the source row of mask m
-                auto product = [&](const KRec& m, int k) {
-                    C s = 0.0;
-                    for (int u = 0; u < PP; ++u) {
-                        const C x = c.far ? vs[u][((uint64_t)(tile ^ m.x_high) << tb) + tid + (uint32_t)k * nt]
-                                          : vs[u][sbase + ((tid + (uint32_t)k * nt) ^ m.xl)];
-                        s += std::conj(gk(u, k)) * x;
-                    }
-                    return s;
-                };
+            auto gk = [&](int u, uint32_t lane, int k) {
+                return lane < (1u << lb) ? wt[u] * gs[u][base + lane + 64u * (uint32_t)k] : C(0.0);
+            };
+            std::vector<int> visits(c.n_quad, 0);
+            for (uint32_t wave = 0; wave < 4; ++wave) {
                 if (c.far) {
-                    for (uint32_t j = c.first; j < c.first + c.count; ++j) {
+                    // every fourth member of the chunk, QUAD only, over all rows of the tile
+                    for (uint32_t j = c.first + wave; j < c.first + c.count; j += 4) {
                         const KRec& m = kr[GC.members[j]];
                         if ((m.meta >> 28) != MASK_QUAD) continue;
                         C a = 0.0;
-                        for (int k = 0; k < RPT; ++k) a += product(m, k);
+                        for (uint32_t lane = 0; lane < (1u << lb); ++lane)
+                            for (int k = 0; k < RPT; ++k)
+                                for (int u = 0; u < PP; ++u)
+                                    a += std::conj(gk(u, lane, k)) *
+                                         vs[u][((uint64_t)(tile ^ m.x_high) << tb) + lane + 64u * (uint32_t)k];
                         if (__builtin_popcount(base & m.zbase) & 1) a = -a;
                         uint32_t idx = 0;
                         for (int q = 0; q < 4; ++q) idx |= ((base >> mask_q(m.qpack, q)) & 1u) << q;
                         bins.at(GC.local[j] + idx) += a;
                     }
-                } else {
-                    uint32_t j = c.first;
-                    for (int cl = 0; cl < ipow3(KB); ++cl) {
-                        const int XK = class_bits(cl, KB, 1), ZK = class_bits(cl, KB, 2);
-                        const int n = (int)((c.cnt[cl >> 2] >> (8 * (cl & 3))) & 0xffu);
-                        for (int i = 0; i < n; ++i, ++j) {
-                            const GRec& q = GC.grec[j];
-                            const uint32_t slot = j - c.first, fo = fold[slot];
-                            auto lane_idx = [&](uint32_t t) {
-                                uint32_t a = 0;
-                                for (int mq = 0; mq < 4; ++mq) {
-                                    const uint32_t b = (q.sel >> (8 * mq)) & 0xffu;
-                                    if (b < 8) a += ((t >> b) & 1u) << mq;
-                                }
-                                return a + (fo & 15u);
-                            };
-                            const uint32_t il = lane_idx(tid);
-                            const uint32_t keep = (q.koffs >> 24) | absent;
+                    continue;
+                }
+                // near QUAD members: positions wave, wave + 4, ... through the classes
+                uint32_t pos = wave, cls_end = 0;
+                for (int cl = 0; cl < ipow3(KB); ++cl) {
+                    const int XK = class_bits(cl, KB, 1), ZK = class_bits(cl, KB, 2);
+                    cls_end += (c.cnt[cl >> 2] >> (8 * (cl & 3))) & 0xffu;
+                    for (; pos < cls_end; pos += 4) {
+                        const uint32_t j = c.first + pos;
+                        ++visits.at(pos);
+                        const GRec& q = GC.grec[j];
+                        if (quad_class(lm[GC.members[j]].x, lm[GC.members[j]].zbase, lb, KB) != cl) ++index_errors;
+                        const uint32_t fo = fold[pos];
+                        auto lane_idx = [&](uint32_t t) {
+                            uint32_t a = 0;
+                            for (int mq = 0; mq < 4; ++mq) {
+                                const uint32_t b = (q.sel >> (8 * mq)) & 0xffu;
+                                if (b < 8) a += ((t >> b) & 1u) << mq;
+                            }
+                            return a + (fo & 15u);
+                        };
+                        const uint32_t keep = q.koffs >> 24;
+                        for (uint32_t lane = 0; lane < 64; ++lane) {
+                            const uint32_t il = lane_idx(lane);
                             // every lane of this lane's group computes the same index
-                            const uint32_t rep = (tid & ~63u) | ((tid & 63u & keep) | (~keep & 15u));
+                            const uint32_t rep = (lane & keep) | (~keep & 15u);
                             if (lane_idx(rep) != il) ++index_errors;
-                            const bool sl = ((__builtin_popcount(tid & q.zl) ^ (fo >> 4)) & 1) != 0;
+                            const bool sl = ((__builtin_popcount(lane & q.zl) ^ (fo >> 4)) & 1) != 0;
                             for (int pp = 0; pp < RPT; ++pp) {
                                 if ((pp & ~XK) != 0) continue;
                                 C e = 0.0;
@@ -174,41 +177,66 @@ int run_case(int N)
                                     if ((k & XK) != pp) continue;
                                     const double neg = (__builtin_popcount((uint32_t)k & (uint32_t)ZK) & 1) ? -1.0 : 1.0;
                                     for (int u = 0; u < PP; ++u) {
-                                        const C x = vs[u][sbase + (tid ^ q.xoff) + ((uint32_t)(k ^ XK) << lb)];
-                                        e += neg * std::conj(gk(u, k)) * x;
+                                        const uint32_t e_src = (lane ^ q.xoff) + ((uint32_t)(k ^ XK) << 6);
+                                        const C x = e_src < tile_rows ? vs[u][sbase + e_src] : C(0.0);
+                                        e += neg * std::conj(gk(u, lane, k)) * x;
                                     }
                                 }
                                 uint32_t idx = il;
                                 for (int b = 0; b < KB; ++b)
                                     if ((pp >> b) & 1) idx += (q.koffs >> (8 * b)) & 0xffu;
-                                bins.at(16 * slot + idx) += sl ? -e : e;
+                                bins.at(16 * pos + idx) += sl ? -e : e;
                             }
                         }
                     }
-                    if (j != c.first + c.n_quad) ++index_errors;   // QUAD members first, all visited
-                }
-                for (uint32_t a = 0; a < c.n_acc; ++a) {
-                    const KRec& m = kr[GC.members[c.first + c.acc[a]]];
-                    for (int k = 0; k < RPT; ++k) acc[(size_t)a * tile_elems + tid + (uint32_t)k * nt] += product(m, k);
                 }
             }
-            // PAIR / DIAG: bin the pair sums row by row
+            if (!c.far)
+                for (uint32_t p = 0; p < c.n_quad; ++p)
+                    if (visits[p] != 1) ++visit_errors;
+            // PAIR / DIAG: thread t sums the rows t and t + 256 over the pairs
+            std::vector<C> rows((size_t)kGradAccMasks * tile_rows, 0.0);
+            for (uint32_t a = 0; a < c.n_acc; ++a) {
+                const KRec& m = kr[GC.members[c.first + c.acc[a]]];
+                for (uint32_t rl = 0; rl < tile_rows; ++rl)
+                    for (int u = 0; u < PP; ++u) {
+                        const C x = c.far ? vs[u][((uint64_t)(tile ^ m.x_high) << tb) + rl] : vs[u][sbase + (rl ^ m.xl)];
+                        rows[(size_t)a * tile_rows + rl] += std::conj(wt[u] * gs[u][base + rl]) * x;
+                    }
+            }
+            // per-tile outputs as the kernel forms them
             for (uint32_t a = 0; a < c.n_acc; ++a) {
                 const KRec& m = kr[GC.members[c.first + c.acc[a]]];
                 C* mb = &bins.at(GC.local[c.first + c.acc[a]]);
-                for (uint32_t rl = 0; rl < tile_elems; ++rl) {
-                    const uint32_t r = base | rl;
-                    const C s = acc[(size_t)a * tile_elems + rl];
-                    if ((m.meta >> 28) == MASK_PAIR) {
-                        const C t = (__builtin_popcount(r & m.zbase) & 1) ? -s : s;
-                        const uint32_t idx = ((r >> mask_q(m.qpack, 0)) & 1u) | (((r >> mask_q(m.qpack, 1)) & 1u) << 1);
-                        mb[idx] += t;
-                        for (int cq = 0; cq < M; ++cq)
-                            if ((r >> cq) & 1u) mb[4 + 4 * cq + idx] += t;
-                    } else {
-                        for (int n = 0; n < T.n_diag; ++n)
-                            mb[n] += (__builtin_popcount(r & T.dz[n]) & 1) ? -s : s;
+                const C* rj = &rows[(size_t)a * tile_rows];
+                if ((m.meta >> 28) == MASK_PAIR) {
+                    const uint32_t q0 = mask_q(m.qpack, 0), q1 = mask_q(m.qpack, 1);
+                    for (uint32_t o = 0; o < 4u * (uint32_t)(tb + 1); ++o) {
+                        const uint32_t idx = o & 3u;
+                        const int cb = (int)(o >> 2) - 1;
+                        C sum = 0.0;
+                        for (int qtr = 0; qtr < 4; ++qtr) {
+                            C part = 0.0;
+                            for (uint32_t rl = qtr * (tile_rows / 4); rl < (qtr + 1) * (tile_rows / 4); ++rl) {
+                                const uint32_t r = base | rl;
+                                if ((((r >> q0) & 1u) | (((r >> q1) & 1u) << 1)) != idx) continue;
+                                if (cb >= 0 && !((rl >> cb) & 1u)) continue;
+                                part += (__builtin_popcount(r & m.zbase) & 1) ? -rj[rl] : rj[rl];
+                            }
+                            sum += part;
+                        }
+                        if (cb >= 0) {
+                            mb[4 + 4 * cb + idx] += sum;
+                        } else {
+                            mb[idx] += sum;
+                            for (int cq = tb; cq < M; ++cq)
+                                if ((base >> cq) & 1u) mb[4 + 4 * cq + idx] += sum;
+                        }
                     }
+                } else {
+                    for (int n = 0; n < T.n_diag; ++n)
+                        for (uint32_t rl = 0; rl < tile_rows; ++rl)
+                            mb[n] += (__builtin_popcount((base | rl) & T.dz[n]) & 1) ? -rj[rl] : rj[rl];
                 }
             }
         }
@@ -226,10 +254,12 @@ int run_case(int N)
         mx = std::max(mx, std::abs(ref[i]));
     }
     const double rel = err / mx;
-    std::printf("N=%d tile_bits=%d rows_per_thread=%d layouts=%d chunks=%zu bins=%llu rel_err=%.3e index_errors=%d\n",
-                N, tb, RPT, two ? 2 : 1, GC.chunks.size(), (unsigned long long)T.n_bins, rel, index_errors);
+    std::printf("N=%d tile_bits=%d rows_per_lane=%d layouts=%d chunks=%zu bins=%llu rel_err=%.3e index_errors=%d "
+                "visit_errors=%d\n",
+                N, tb, RPT, two ? 2 : 1, GC.chunks.size(), (unsigned long long)T.n_bins, rel, index_errors,
+                visit_errors);
     std::fflush(stdout);
-    return (rel < 1e-12 && index_errors == 0) ? 0 : 1;
+    return (rel < 1e-12 && index_errors == 0 && visit_errors == 0) ? 0 : 1;
 }
 
 }  // namespace
@@ -237,6 +267,6 @@ int run_case(int N)
 int main()
 {
     int bad = 0;
-    for (int N : {16, 20, 28, 34}) bad += run_case(N);
+    for (int N : {8, 12, 16, 20, 28, 34}) bad += run_case(N);
     return bad;
 }

@@ -108,8 +108,8 @@ def test_autograd_function_matches():
     F, g = autograd.otoc_value_and_grad(J, N, 0, 1, 2.0, 0.3, psi, o)
     T = api.Terms(N, J)
     F2, g2 = api.grad_couplings(T, 0, 1, 2.0, 0.3, psi, o)
-    # the bins' LDS atomics add in run-dependent order: equal to rounding
-    assert F == F2 and np.abs(g - g2).max() <= 1e-12 * np.abs(g2).max()
+    # every reduction runs in a fixed order: the same bits
+    assert F == F2 and np.array_equal(g, g2)
     Jt = torch.from_numpy(J)
     assert abs(float(autograd.ChebOTOC.apply(Jt, N, 0, 1, 2.0, 0.3, psi, o)) - F) == 0.0
 
@@ -156,6 +156,38 @@ def test_coupling_overlaps_vs_checker(N, count):
     T.close()
 
 
+def test_grad_vs_finite_differences_cfg4_schedule_n28():
+    """The gradient workload's full schedule (beta J = 5, t* = 6, Chebyshev
+    degree 32, dt = 0.1, a checkpoint every 10 operations) at N = 28: 50
+    couplings drawn as for the workload (seed 4, without replacement) against
+    central differences with h = 1e-6 of the GPU forward."""
+    N = 28
+    J = inputs.couplings(N, 0)
+    psi = _gpu(inputs.typical_state(N, 1))
+    T = api.Terms(N, J)
+    lo, hi = api.spectrum_bounds(T, psi, 60)
+    o = api.cheb_opts(degree=32, dt=0.1, tau_steps=1, checkpoint_every=10, e_halfwidth=1.1 * max(abs(lo), abs(hi)))
+    F, g = api.grad_couplings(T, 0, 1, 5.0, 6.0, psi, o)
+    ks = np.random.default_rng(4).choice(len(J), 50, replace=False)
+    h = 1e-6
+    tol = 1e-6 * np.abs(g).max() + 1e-9
+    worst = 0.0
+    for n, k in enumerate(ks):
+        vals = []
+        for s in (1.0, -1.0):
+            Jp = J.copy()
+            Jp[k] += s * h
+            Tp = api.Terms(N, Jp)
+            vals.append(api.cheb_otoc(Tp, 0, 1, 5.0, 6.0, psi, o))
+            Tp.close()
+        fd = (vals[0] - vals[1]) / (2 * h)
+        worst = max(worst, abs(fd - g[k]))
+        if n % 10 == 9:
+            print(f"[grad-fd] {n + 1}/50 couplings, worst |g - fd| {worst:.2e} (tol {tol:.2e})", flush=True)
+    assert worst <= tol
+    T.close()
+
+
 def test_grad_vs_finite_differences_n36():
     """Sampled couplings at N=36 (masks in both row layouts) against central
     differences of the GPU forward."""
@@ -184,20 +216,25 @@ def test_grad_vs_finite_differences_n36():
 
 def test_grad_euler_identity_n44():
     """The gradient workload's size (N=44, dim 2^22, 135,751 couplings, masks in
-    two row layouts) on a short schedule: sum_k J_k dF/dJ_k = beta dF/dbeta +
-    t dF/dt, an exact property of F (H is linear in J) that checks every
-    coupling's derivative at once."""
+    two row layouts) with its step, degree and checkpoint interval (dt = 0.1,
+    degree 32, a checkpoint every 10 operations) on t* = 1, so that each chain
+    (25 operations) is swept back through three checkpoint segments:
+    sum_k J_k dF/dJ_k = beta dF/dbeta + t dF/dt, an exact property of F (H is
+    linear in J) that checks every coupling's derivative at once."""
     N = 44
     J = inputs.couplings(N, 0)
     psi = _gpu(inputs.typical_state(N, 1))
     T = api.Terms(N, J)
     lo, hi = api.spectrum_bounds(T, psi, 60)
     e_h = 1.2 * max(abs(lo), abs(hi))
-    beta, t, n = 5.0, 0.2, 2
+    beta, t, n = 5.0, 1.0, 10
     opts = lambda tt: api.cheb_opts(degree=32, dt=tt / n, tau_steps=1, checkpoint_every=10, e_halfwidth=e_h)
+    print("[grad-n44] gradient", flush=True)
     F, g = api.grad_couplings(T, 0, 1, beta, t, psi, opts(t))
     d = 1e-4
+    print("[grad-n44] forwards at beta +- d", flush=True)
     Fb = [api.cheb_otoc(T, 0, 1, beta + s * d, t, psi, opts(t)) for s in (1, -1)]
+    print("[grad-n44] forwards at t +- d", flush=True)
     Ft = [api.cheb_otoc(T, 0, 1, beta, t + s * d, psi, opts(t + s * d)) for s in (1, -1)]
     rhs = beta * (Fb[0] - Fb[1]) / (2 * d) + t * (Ft[0] - Ft[1]) / (2 * d)
     assert abs(np.dot(J, g) - rhs) <= 1e-7
@@ -207,10 +244,9 @@ def test_grad_euler_identity_n44():
 @pytest.mark.parametrize("N,ck", [(16, 3), (36, 4)])
 def test_grad_kept_segments_identical(N, ck):
     """The reverse sweep with a segment's Chebyshev vectors kept from its
-    recomputation gives the F and gradient of recomputing them per step (same
-    kernels on the same vectors; the bins' LDS atomics from several waves add in
-    run-dependent order, so the gradient agrees to rounding), including a ragged
-    last segment."""
+    recomputation gives the F and gradient of recomputing them per step, bit
+    for bit (same kernels on the same vectors, fixed-order reductions),
+    including a ragged last segment."""
     J = inputs.couplings(N, 0)
     psi = _gpu(inputs.typical_state(N, 1))
     T = api.Terms(N, J)
@@ -221,5 +257,19 @@ def test_grad_kept_segments_identical(N, ck):
         o = api.cheb_opts(degree=16, dt=0.1, tau_steps=2, checkpoint_every=ck, e_halfwidth=e_h, keep_segment=keep)
         out.append(api.grad_couplings(T, 0, 1, 2.0, 0.3, psi, o))
     assert out[0][0] == out[1][0]
-    assert np.abs(out[0][1] - out[1][1]).max() <= 1e-12 * np.abs(out[0][1]).max()
+    assert np.array_equal(out[0][1], out[1][1])
+    T.close()
+
+
+@pytest.mark.parametrize("N", [20, 36])
+def test_coupling_overlaps_bitwise_repeatable(N):
+    """The per-coupling reductions give the same bits on every call (no float
+    atomics: each bin is added to by one wave, PAIR and DIAG bins by fixed
+    threads in a fixed order, slices summed in a fixed order)."""
+    host = [(inputs.typical_state(N, 40 + p), inputs.typical_state(N, 50 + p), w)
+            for p, w in enumerate((1.0, -0.5, 0.25, 2.0, -1.5))]
+    T = api.Terms(N, inputs.couplings(N, 0))
+    pairs = [(_gpu(g), _gpu(v), w) for g, v, w in host]
+    runs = [api.coupling_overlaps(T, pairs) for _ in range(3)]
+    assert np.array_equal(runs[0], runs[1]) and np.array_equal(runs[0], runs[2])
     T.close()

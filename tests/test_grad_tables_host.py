@@ -1,13 +1,15 @@
 """Host check of the derivative-bin kernel's tables, without a GPU.
 
 tests/host/grad_tables_emu.cpp builds the gradient chunk tables with the
-library's host code (the gradient's launch shape; one row layout at N = 16, 20,
-28 and two at N = 34) and evaluates the bins of two weighted (g, v) pairs from
-them the way k_grad_bins reads them: near chunks with QUAD members by row class
-and the per-tile fold, far chunks, PAIR and DIAG sums binned per row.  It
+library's host code (the gradient's launch shape: 512-row tiles, fewer rows
+for small states; one row layout at N = 8 ... 28 and two at N = 34) and
+evaluates the bins of two weighted (g, v) pairs from them the way k_grad_bins
+reads them: each wave's share of a near chunk's QUAD members by row class with
+the per-tile fold, far chunks, and the per-tile PAIR and DIAG outputs.  It
 compares with the bins' definitions and checks that all lanes of an in-wave
-sum group compute the same bin index.  The kernel source is compiled with
-hipcc (device code included); nothing runs on a GPU.
+sum group compute the same bin index and that each QUAD member is visited by
+exactly one wave per tile.  The kernel source is compiled with hipcc (device
+code included); nothing runs on a GPU.
 """
 import os
 import subprocess
@@ -35,5 +37,5 @@ def test_grad_tables_match_bin_definitions(tmp_path):
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr[-2000:]
     lines = [ln for ln in r.stdout.splitlines() if ln.startswith("N=")]
-    assert len(lines) == 4
+    assert len(lines) == 6
     assert "layouts=2" in lines[-1]
