@@ -327,7 +327,8 @@ syk_status syk_cheb_otoc(syk_terms t, int i, int j, double beta, double t_star, 
  * through every Chebyshev step (Clenshaw's recurrence for the adjoint states)
  * with states recomputed from checkpoints, and per-coupling reductions
  * Re <g| dH/dJ v> accumulated on the device.  Includes the derivative of
- * <psi|rho|psi>.
+ * <psi|rho|psi>.  With the environment variable SYK_PROGRESS set, each
+ * finished checkpoint segment of the reverse sweep is reported on stderr.
  */
 syk_status syk_grad_couplings(syk_terms t, int i, int j, double beta, double t_star, const syk_cheb_opts* opts,
                               const void* psi0, double* F, double* dF_dJ, hipStream_t stream);

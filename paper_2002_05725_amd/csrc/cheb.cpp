@@ -18,12 +18,26 @@
 #include "cheb.hpp"
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 namespace syk {
 
 namespace {
 
 typedef std::complex<double> C;
+
+// With SYK_PROGRESS set in the environment, long gradient calls report each
+// finished checkpoint segment of the reverse sweep on stderr (after waiting for
+// the segment's device work).
+void progress(const char* what, const std::string& chain, int done, int total, hipStream_t s)
+{
+    static const bool on = std::getenv("SYK_PROGRESS") != nullptr;
+    if (!on) return;
+    (void)hipStreamSynchronize(s);
+    std::fprintf(stderr, "[syk] %s %s: %d/%d\n", what, chain.c_str(), done, total);
+    std::fflush(stderr);
+}
 
 struct Pool {
     syk_terms_s& h;
@@ -172,6 +186,7 @@ void chain_backward(Stepper& st, const std::vector<ChebOp>& ops, const std::stri
     st.c.ops.copy(lam, seed);
     const int nseg = (L + Ck - 1) / Ck;
     for (int sg = nseg - 1; sg >= 0; --sg) {
+        progress("reverse sweep", ckpt_name, nseg - 1 - sg, nseg, st.c.stream);
         const int l0 = sg * Ck, l1 = std::min(L, l0 + Ck);
         // inputs of operations l0 .. l1-1 (and, kept, every step's vectors)
         st.c.ops.copy(st.pool.get("in", 0), st.pool.get(ckpt_name, sg));
@@ -270,7 +285,9 @@ void cheb_otoc(BlockCtx& c, int i, int j, double beta, double t, const ChebSetti
     void* B = pool.get("B");
     void* u = pool.get("u");
     chain_forward(st, ch.A, psi0, A, g ? "ckA" : "");
+    progress("forward", "A", 1, 1, c.stream);
     chain_forward(st, ch.B, psi0, B, g ? "ckB" : "");
+    progress("forward", "B", 1, 1, c.stream);
     chain_forward(st, ch.U, psi0, u, g ? "ckU" : "");
     const double Z = c.ops.norm2(u)[0];
     const double num = c.ops.multidot(B, 1, A)[0].real();
