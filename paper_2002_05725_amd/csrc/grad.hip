@@ -187,8 +187,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     constexpr int RPT = 1 << KB;
     constexpr int PP = kGradPairsPerStage;
     constexpr int TS = kGradTileRows;                        // LDS rows per staged pair (the largest tile)
-    constexpr int SR = PP > kGradAccMasks ? PP : kGradAccMasks;
-    __shared__ __align__(16) c128 src[SR * TS];           // source rows; the PAIR / DIAG row sums at tile end
+    constexpr int SS = PP * TS;                              // one staged source tile of PP pairs
+    constexpr int SR = kGradSrcTiles * PP > kGradAccMasks ? kGradSrcTiles * PP : kGradAccMasks;
+    __shared__ __align__(16) c128 src[SR * TS];           // [slot][pair][row] source rows; PAIR / DIAG row sums
+                                                           // at tile end
     __shared__ __align__(16) double bins[2 * kGradBinCap];
     __shared__ uint32_t fold[kChunkMasks + 4];
     __shared__ __align__(16) double part[2 * 4 * kGradPairOutputs];   // PAIR outputs of four row quarters
@@ -249,17 +251,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                     }
                 }
                 if (!C.far) {
-                    // the chunk's source tile; rows past a tiny state are zeros
+                    // the chunk's source tiles; rows past a tiny state are zeros
                     __syncthreads();   // previous users of src are done
-                    const uint64_t sbase = (uint64_t)(tile ^ C.x_high) << L.tile_bits;
 #pragma unroll
-                    for (int u = 0; u < PP; ++u) {
-                        const c128* __restrict__ v = vs[p0 + u];
+                    for (int sl = 0; sl < kGradSrcTiles; ++sl) {
+                        if (sl >= (int)C.n_src) break;
+                        const uint64_t sbase = (uint64_t)(tile ^ (sl ? C.x_high2 : C.x_high)) << L.tile_bits;
 #pragma unroll
-                        for (int e = (int)tid; e < TS; e += 256) {
-                            c128 x{0.0, 0.0};
-                            if ((uint32_t)e < tile_rows) x = v[sbase + (uint32_t)e];
-                            src[u * TS + e] = x;
+                        for (int u = 0; u < PP; ++u) {
+                            const c128* __restrict__ v = vs[p0 + u] + sbase;
+#pragma unroll
+                            for (int h = 0; h < TS / 256; ++h) {
+                                const uint32_t e = tid + 256u * h;
+                                c128& d = src[sl * SS + u * TS + e];
+                                if (e < tile_rows) {
+                                    d = v[e];
+                                } else {
+                                    d.re = 0.0;
+                                    d.im = 0.0;
+                                }
+                            }
                         }
                     }
                     __syncthreads();
@@ -317,11 +328,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                             const uint32_t il = __builtin_amdgcn_udot4(__builtin_amdgcn_perm(B1, B0, q.sel), 0x08040201u,
                                                                        fo & 15u, false);
                             const uint32_t sl = (((uint32_t)__popc(lane & q.zl) ^ (fo >> 4)) & 1u) << 31;
-                            const uint32_t keep = q.koffs >> 24;
+                            const uint32_t keep = (q.koffs >> 24) & 63u;
                             double er[RPT], ei[RPT];   // by the flipped k bits p = k & XK
 #pragma unroll
                             for (int pp = 0; pp < RPT; ++pp) er[pp] = ei[pp] = 0.0;
-                            const uint32_t sb = lane ^ q.xoff;
+                            // lane part of the source row, in the member's staged tile
+                            const uint32_t sb = (lane ^ q.xoff) + ((q.koffs >> 30) & 1u) * SS;
                             // source rows of row k (both pairs), read kAhead rows before their FMAs
                             constexpr int kAhead = 2;
                             c128 xs[kAhead + 1][PP];
@@ -412,6 +424,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 for (int j = 0; j < kGradAccMasks; ++j) {
                     if (j >= (int)C.n_acc) break;
                     const KRec ma = krec[members[C.first + C.acc[j]]];
+                    const uint32_t slot_off = ((grec[C.first + C.acc[j]].koffs >> 30) & 1u) * SS;
 #pragma unroll
                     for (int k = 0; k < RPT; ++k) {
                         if ((uint32_t)(k & 3) != wave || !live) continue;
@@ -421,7 +434,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 #pragma unroll
                         for (int u = 0; u < PP; ++u) {
                             const c128 x = C.far ? vs[p0 + u][((uint64_t)(tile ^ ma.x_high) << L.tile_bits) + rl]
-                                                 : src[u * TS + (rl ^ ma.xl)];
+                                                 : src[slot_off + u * TS + (rl ^ ma.xl)];
                             ar = fma(gk[u][k].re, x.re, fma(gk[u][k].im, x.im, ar));
                             ai = fma(gk[u][k].re, x.im, fma(-gk[u][k].im, x.re, ai));
                         }
@@ -564,17 +577,27 @@ GradChunks make_grad_chunks(const std::vector<MaskRec>& masks, const std::vector
         const bool accm = type != MASK_QUAD;
         const bool is_far = type != MASK_DIAG && (masks[i].x & row_mask) == 0u;
         std::vector<Build>& out = is_far ? far : near;
-        const bool same = !out.empty() && out.back().c.layout == layout_of[i] && (is_far || out.back().c.x_high == xh);
+        // a near chunk takes a second source tile when its first group of masks ends
+        bool same = !out.empty() && out.back().c.layout == layout_of[i];
+        if (same && !is_far) {
+            const GChunk& c = out.back().c;
+            same = c.x_high == xh || (c.n_src == 2 && c.x_high2 == xh) || c.n_src < (uint32_t)kGradSrcTiles;
+        }
         if (!same || out.back().c.count == (uint32_t)kChunkMasks ||
             out.back().c.bin_count + nb > (uint64_t)kGradBinCap ||
             (accm && out.back().c.n_acc == (uint32_t)kGradAccMasks)) {
             Build b{};
             b.c.x_high = is_far ? 0u : xh;
+            b.c.n_src = is_far ? 0u : 1u;
             b.c.far = is_far ? 1u : 0u;
             b.c.layout = layout_of[i];
             out.push_back(b);
         }
         Build& b = out.back();
+        if (!is_far && b.c.x_high != xh && (b.c.n_src < 2 || b.c.x_high2 != xh)) {
+            b.c.x_high2 = xh;
+            b.c.n_src = 2;
+        }
         if (accm) ++b.c.n_acc;
         b.mem.push_back(i);
         ++b.c.count;
@@ -597,6 +620,8 @@ GradChunks make_grad_chunks(const std::vector<MaskRec>& masks, const std::vector
             const uint32_t i = b.mem[pos];
             const MaskRec& m = masks[i];
             GRec r{};
+            // which of the chunk's staged source tiles the member reads
+            if (!b.c.far && (m.x >> tile_bits) != b.c.x_high) r.koffs |= 1u << 30;
             if ((m.type_tab >> 28) == MASK_QUAD) {
                 ++b.c.n_quad;
                 if (!b.c.far) {

@@ -120,7 +120,12 @@ int run_case(int N)
                     for (int q = 0; q < 4; ++q) qi |= ((base >> mask_q(m.qpack, q)) & 1u) << q;
                     fold[j] = qi | ((uint32_t)(__builtin_popcount(base & m.zbase) & 1) << 4);
                 }
-            const uint64_t sbase = (uint64_t)(tile ^ c.x_high) << tb;
+            // the staged source tile a member reads: bit 30 of its koffs picks one of the chunk's two
+            auto sbase_of = [&](uint32_t j) {
+                const uint32_t xh = ((GC.grec[j].koffs >> 30) & 1u) ? c.x_high2 : c.x_high;
+                if (!c.far && ((kr[GC.members[j]].x_high) != xh)) ++index_errors;
+                return (uint64_t)(tile ^ xh) << tb;
+            };
             auto gk = [&](int u, uint32_t lane, int k) {
                 return lane < (1u << lb) ? wt[u] * gs[u][base + lane + 64u * (uint32_t)k] : C(0.0);
             };
@@ -163,7 +168,8 @@ int run_case(int N)
                             }
                             return a + (fo & 15u);
                         };
-                        const uint32_t keep = q.koffs >> 24;
+                        const uint32_t keep = (q.koffs >> 24) & 63u;
+                        const uint64_t sbase = sbase_of(j);
                         for (uint32_t lane = 0; lane < 64; ++lane) {
                             const uint32_t il = lane_idx(lane);
                             // every lane of this lane's group computes the same index
@@ -198,6 +204,7 @@ int run_case(int N)
             std::vector<C> rows((size_t)kGradAccMasks * tile_rows, 0.0);
             for (uint32_t a = 0; a < c.n_acc; ++a) {
                 const KRec& m = kr[GC.members[c.first + c.acc[a]]];
+                const uint64_t sbase = c.far ? 0 : sbase_of(c.first + c.acc[a]);
                 for (uint32_t rl = 0; rl < tile_rows; ++rl)
                     for (int u = 0; u < PP; ++u) {
                         const C x = c.far ? vs[u][((uint64_t)(tile ^ m.x_high) << tb) + rl] : vs[u][sbase + (rl ^ m.xl)];
