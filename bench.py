@@ -142,7 +142,10 @@ def batched_leg(api, inputs, torch, np, dev, N, m, dt):
     one 64-column block, the regularized OTOC at beta J = 5 on the output
     window t in {0, 0.5} (Lanczos m, real step dt, imaginary step 0.625): the
     complex64 block (FP64 inner products), the complex128 block, and one
-    column alone in complex128 (the plain path), all on the same GPU."""
+    column alone in complex128 (the plain path), all on the same GPU.  The
+    apply runs in its automatic shape: the complex64 block with the two
+    columns of each realisation in one workgroup, complex128 one column per
+    workgroup."""
     R = 32
     times, beta, tau = [0.0, 0.5], 5.0, 0.625
     Js = np.stack([inputs.couplings(N, inputs.batch_coupling_seed(N, r)) for r in range(R)])
@@ -150,7 +153,7 @@ def batched_leg(api, inputs, torch, np, dev, N, m, dt):
     real = np.repeat(np.arange(R), 2)
     host = np.stack([inputs.typical_state(N, inputs.batch_state_seed(N, r, s)) for r in range(R) for s in range(2)])
     out = {"N": N, "columns": 64, "realisations": R, "m": m, "dt": dt, "tau_step": tau, "beta": beta,
-           "times": times}
+           "times": times, "apply_columns_per_workgroup": {"block_c64": 2, "block_c128": 1, "single_c128": 1}}
     flops_apply = FLOPS_PER_PAIR * T.n_masks * T.dim
     F = {}
     for name, dtp, x_host, rc, cols in (("block_c64", torch.complex64, host, real, 64),
@@ -371,6 +374,10 @@ def main():
                          "(for hardware-counter runs), then exit")
     ap.add_argument("--profile-dtype", choices=("c128", "c64"), default="c128",
                     help="state precision of the --profile-apply calls")
+    ap.add_argument("--profile-block", type=int, default=0,
+                    help="only run this many apply_H calls on the batched leg's 64-column block (--batch-N, "
+                         "--profile-dtype) with one column per workgroup, then as many with two columns of "
+                         "one realisation per workgroup (2048-row tiles), and exit (for kernel-trace runs)")
     ap.add_argument("--profile-bins", type=int, default=0,
                     help="only run this many derivative-bin calls (32 pairs of seeded random states at the "
                          "gradient leg's N) and exit (for kernel-trace and counter runs)")
@@ -389,6 +396,23 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     dev = torch.device("cuda:0")
+    if args.profile_block > 0:
+        Nk, R = args.batch_N, 32
+        Tk = api.Terms(Nk, np.stack([inputs.couplings(Nk, inputs.batch_coupling_seed(Nk, r)) for r in range(R)]))
+        real = np.repeat(np.arange(R), 2)
+        dtp = torch.complex128 if args.profile_dtype == "c128" else torch.complex64
+        x = torch.from_numpy(np.stack([inputs.typical_state(Nk, inputs.batch_state_seed(Nk, r, s))
+                                       for r in range(R) for s in range(2)])).to(dev).to(dtp)
+        out = torch.empty_like(x)
+        for nc in (1, 2):
+            api.set_apply_tuning(Tk, 11, 1, nc)
+            for k in range(args.profile_block):
+                api.apply_H(Tk, x, out, real_of_col=real)
+                torch.cuda.synchronize()
+                log(f"[bench] block apply, {nc} column(s) per workgroup: {k + 1}/{args.profile_block} done")
+        print(json.dumps({"profile_block": args.profile_block, "dtype": args.profile_dtype, "N": Nk,
+                          "columns": 64, "realisations": R}), flush=True)
+        return
     if args.profile_bins > 0:
         Nb = args.grad_N
         Tb = api.Terms(Nb, inputs.couplings(Nb, 0))

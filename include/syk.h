@@ -113,9 +113,17 @@ syk_status syk_apply_H_noalloc(syk_terms t, syk_dtype dtype, int nvec, const int
  * workgroup owns 2^tile_bits rows (0 = automatic, else at most 11; capped at
  * the number of qubits) with min(256, 2^tile_bits) threads, each thread up to 8
  * rows.  xcd_remap = 1 hands each of the 8 XCDs a contiguous range of row
- * tiles, 0 keeps the hardware's round-robin order.  Other values give
- * SYK_EINVAL and leave the setting unchanged. */
-syk_status syk_set_apply_tuning(syk_terms t, int tile_bits, int xcd_remap);
+ * tiles, 0 keeps the hardware's round-robin order.  cols_per_group = 2 lets one
+ * workgroup serve two consecutive columns of a block that share a realisation
+ * (the two typical states of one disorder draw), decoding every mask once for
+ * both; it needs tile_bits 10 or 11 (or automatic, where smaller tiles fall
+ * back to one column), and a launch whose columns do not pair up by
+ * realisation runs one column per workgroup.  1: one column per workgroup.
+ * 0 (automatic): two for complex64, one for complex128.  The product is the
+ * same in every shape up to the order of floating-point sums (and bit for bit
+ * between one and two columns per workgroup on the same tiles).  Other values give SYK_EINVAL and leave the setting
+ * unchanged. */
+syk_status syk_set_apply_tuning(syk_terms t, int tile_bits, int xcd_remap, int cols_per_group);
 
 /* Cap on the device workspace a handle may hold (Krylov basis, estimator
  * vectors, Chebyshev stacks, checkpoints, rotated-layout copies of the

@@ -49,7 +49,7 @@ _SIGS = {
                             ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "syk_apply_H": (_i, [_vp, _i, _i, _vp, _vp, _vp, _vp]),
     "syk_apply_H_noalloc": (_i, [_vp, _i, _i, _vp, _vp, _vp, _vp]),
-    "syk_set_apply_tuning": (_i, [_vp, _i, _i]),
+    "syk_set_apply_tuning": (_i, [_vp, _i, _i, _i]),
     "syk_set_workspace_limit": (_i, [_vp, ctypes.c_uint64]),
     "syk_timing_enable": (_i, [_i]),
     "syk_timing_read": (_i, [ctypes.POINTER(_i64), ctypes.POINTER(_d)]),

@@ -106,9 +106,10 @@ class Terms:
             pass
 
 
-def set_apply_tuning(terms: Terms, tile_bits: int = 0, xcd_remap: int = 1):
+def set_apply_tuning(terms: Terms, tile_bits: int = 0, xcd_remap: int = 1, cols_per_group: int = 0):
     """Launch shape of apply_H for this handle (0 = automatic); see syk_set_apply_tuning."""
-    check(lib().syk_set_apply_tuning(terms.handle, int(tile_bits), int(xcd_remap)), "syk_set_apply_tuning")
+    check(lib().syk_set_apply_tuning(terms.handle, int(tile_bits), int(xcd_remap), int(cols_per_group)),
+          "syk_set_apply_tuning")
 
 
 def set_workspace_limit(terms: Terms, nbytes: int):

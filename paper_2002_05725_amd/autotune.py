@@ -2,9 +2,10 @@
 
 Knobs (syk_set_apply_tuning): the tile of rows a workgroup owns (2^tile_bits
 rows; 256 threads own up to 8 rows each, so tile_bits 8..11 chooses the rows
-per thread 1..8 and the width of the LDS source tile) and the order in which
+per thread 1..8 and the width of the LDS source tile), the order in which
 tiles are handed to the 8 XCDs (contiguous ranges per XCD, or the hardware's
-round robin).  Each candidate is timed with the library's HIP-event timing of
+round robin) and, for blocks of an even number of columns, whether one
+workgroup serves two columns of one realisation (tile_bits 10 and 11).  Each candidate is timed with the library's HIP-event timing of
 apply_H on the handle's own tables for the requested block width and dtype,
 the fastest is installed on the handle, and the choice is cached in a JSON file
 keyed by (device architecture, N, dtype, block width), so a later run installs
@@ -25,12 +26,18 @@ from . import api
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2002_05725_amd", "apply_tuning.json")
 
 
-def candidates(N: int) -> list[tuple[int, int]]:
-    """(tile_bits, xcd_remap) pairs valid for N Majoranas (M = N/2 qubits):
-    tiles of 2^8 .. 2^11 rows (fewer when M is smaller), both tile orders."""
+def candidates(N: int, nvec: int = 1) -> list[tuple[int, int, int]]:
+    """(tile_bits, xcd_remap, cols_per_group) triples valid for N Majoranas
+    (M = N/2 qubits) and a block of nvec columns: tiles of 2^8 .. 2^11 rows
+    (fewer when M is smaller), both tile orders, one column per workgroup, and
+    for an even nvec also two columns per workgroup on tiles of 2^10 and 2^11
+    rows."""
     M = N // 2
     tbs = [tb for tb in (8, 9, 10, 11) if tb <= M] or [M]
-    return [(tb, x) for tb in tbs for x in (1, 0)]
+    out = [(tb, x, 1) for tb in tbs for x in (1, 0)]
+    if nvec >= 2 and nvec % 2 == 0:
+        out += [(tb, x, 2) for tb in tbs if tb >= 10 for x in (1, 0)]
+    return out
 
 
 def cache_key(arch: str, N: int, dtype: torch.dtype, nvec: int) -> str:
@@ -69,11 +76,11 @@ def _arch() -> str:
 
 
 def time_shape(terms: api.Terms, x: torch.Tensor, y: torch.Tensor, tile_bits: int, xcd_remap: int,
-               reps: int) -> float:
+               reps: int, cols_per_group: int = 1) -> float:
     """Average ms of one apply_H call on x (HIP events on the call's stream)
     with this launch shape; the first call (which builds the shape's tables) is
     not timed."""
-    api.set_apply_tuning(terms, tile_bits, xcd_remap)
+    api.set_apply_tuning(terms, tile_bits, xcd_remap, cols_per_group)
     api.apply_H(terms, x, y)
     torch.cuda.synchronize()
     api.timing_reset()
@@ -92,12 +99,13 @@ def time_shape(terms: api.Terms, x: torch.Tensor, y: torch.Tensor, tile_bits: in
 
 
 def tune_apply(terms: api.Terms, dtype: torch.dtype = torch.complex128, nvec: int = 1, reps: int = 3,
-               cache: str | None = DEFAULT_CACHE, shapes: list[tuple[int, int]] | None = None,
+               cache: str | None = DEFAULT_CACHE, shapes: list[tuple[int, int, int]] | None = None,
                use_cache: bool = True) -> dict:
     """Chooses and installs the apply_H launch shape for `terms`, `dtype` and a
-    block of `nvec` columns.  With use_cache and a cached entry for this key,
-    installs that entry without timing.  Returns the chosen entry
-    {"tile_bits", "xcd_remap", "ms", "timed": [...]}."""
+    block of `nvec` columns (timed with every column in realisation 0, so
+    that two-column shapes apply).  With use_cache and a cached entry for this
+    key, installs that entry without timing.  Returns the chosen entry
+    {"tile_bits", "xcd_remap", "cols_per_group", "ms", "timed": [...]}."""
     if dtype not in (torch.complex128, torch.complex64):
         raise ValueError("dtype must be complex128 or complex64")
     if nvec < 1 or reps < 1:
@@ -106,19 +114,20 @@ def tune_apply(terms: api.Terms, dtype: torch.dtype = torch.complex128, nvec: in
     if cache and use_cache:
         hit = read_cache(cache).get(key)
         if hit is not None:
-            api.set_apply_tuning(terms, hit["tile_bits"], hit["xcd_remap"])
+            api.set_apply_tuning(terms, hit["tile_bits"], hit["xcd_remap"], hit.get("cols_per_group", 1))
             return hit
     shape = (terms.dim,) if nvec == 1 else (nvec, terms.dim)
     g = torch.Generator(device="cuda").manual_seed(0)
     x = torch.randn(shape, dtype=dtype, device="cuda", generator=g)
     y = torch.empty_like(x)
     timed = []
-    for tb, xr in (shapes or candidates(terms.N)):
-        timed.append({"tile_bits": tb, "xcd_remap": xr, "ms": time_shape(terms, x, y, tb, xr, reps)})
+    for tb, xr, nc in (shapes or candidates(terms.N, nvec)):
+        timed.append({"tile_bits": tb, "xcd_remap": xr, "cols_per_group": nc,
+                      "ms": time_shape(terms, x, y, tb, xr, reps, nc)})
     del x, y
     best = dict(pick(timed))
     best["timed"] = timed
-    api.set_apply_tuning(terms, best["tile_bits"], best["xcd_remap"])
+    api.set_apply_tuning(terms, best["tile_bits"], best["xcd_remap"], best["cols_per_group"])
     if cache:
         write_cache(cache, key, best)
     return best

@@ -235,17 +235,19 @@ syk_status syk_apply_H_sector(syk_terms t, syk_dtype dtype, int sector, int nvec
     });
 }
 
-syk_status syk_set_apply_tuning(syk_terms t, int tile_bits, int xcd_remap)
+syk_status syk_set_apply_tuning(syk_terms t, int tile_bits, int xcd_remap, int cols_per_group)
 {
     return guard([&] {
         check_handle(t);
         require(tile_bits >= 0 && tile_bits <= 11, "tile_bits must be in [0, 11]");
         require(xcd_remap == 0 || xcd_remap == 1, "xcd_remap must be 0 or 1");
+        require(cols_per_group >= 0 && cols_per_group <= 2, "cols_per_group must be 0, 1 or 2");
         const bool o_tuned = t->tuned;
-        const int o_tb = t->tune_tile_bits, o_x = t->tune_xcd;
+        const int o_tb = t->tune_tile_bits, o_x = t->tune_xcd, o_c = t->tune_cols;
         t->tuned = true;
         t->tune_tile_bits = tile_bits;
         t->tune_xcd = xcd_remap;
+        t->tune_cols = cols_per_group;
         try {
             (void)plan_for(*t, 1, SYK_C128);   // reject shapes that cannot launch
             (void)plan_for(*t, 1, SYK_C64);
@@ -253,6 +255,7 @@ syk_status syk_set_apply_tuning(syk_terms t, int tile_bits, int xcd_remap)
             t->tuned = o_tuned;
             t->tune_tile_bits = o_tb;
             t->tune_xcd = o_x;
+            t->tune_cols = o_c;
             throw;
         }
     });

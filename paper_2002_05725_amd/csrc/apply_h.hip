@@ -9,10 +9,13 @@
 // from LDS, and each thread keeps its rows' sums in registers and writes them
 // once.
 //
-// Grid: (tiles, columns); every workgroup serves one column and that column's
-// realisation, so mask records, PAIR weights and DIAG terms are wave-uniform
-// (scalar loads) and the chunk's QUAD tables are staged into LDS next to the
-// source tile.  Up to 64 columns per launch.
+// Grid: (tiles, column groups); every workgroup serves NC consecutive columns
+// of one realisation (NC = 1, or 2 for the two typical states a realisation
+// carries in a block), so mask records, PAIR weights and DIAG terms are
+// wave-uniform (scalar loads) and the chunk's QUAD tables are staged into LDS
+// next to the NC source tiles.  Everything a mask decodes (record, table
+// entries, lane index and sign, PAIR coefficients) is formed once and applied
+// to every column.  Up to 64 columns per launch.
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -44,7 +47,7 @@ struct KLayout {
     int tile_bits;     // rows per tile = 2^tile_bits
     int lane_bits;     // threads per workgroup = 2^lane_bits
     uint64_t dim;      // rows per column
-    int col0;          // first column of this launch (column = col0 + blockIdx.y)
+    int col0;          // first column of this launch (column = col0 + NC blockIdx.y + c)
     uint32_t n_tiles;  // dim >> tile_bits
     int xcd_remap;     // spread consecutive tiles over XCDs in contiguous ranges
     int32_t real[kColsPerLaunch];  // realisation of each column of the launch
@@ -102,11 +105,19 @@ constexpr int kLaneBits = 8;
 // 2048-row tile at 40 KiB so that four workgroups share a CU.
 constexpr int apply_chunk_masks(uint32_t esz) { return esz == 16 ? 32 : 64; }
 
-template <typename R, int RPT>
+template <typename R, int RPT, int NC>
 struct ApplyLds {
-    cplx<R> src[RPT << kLaneBits];
+    cplx<R> src[NC * (RPT << kLaneBits)];   // column c's tile at c * (RPT << kLaneBits)
     cplx<R> tabs[apply_chunk_masks(sizeof(cplx<R>)) * 16];
 };
+
+// Waves per SIMD the kernel is compiled for: four with one column and 8 rows
+// per thread; two columns double the sums (three waves for complex64, two for
+// complex128, whose two 32 KiB tiles allow two workgroups per CU anyway).
+constexpr int apply_waves(int rpt, int nc, int rbytes)
+{
+    return rpt != 8 ? 1 : nc == 1 ? 4 : rbytes == 8 ? 2 : 3;
+}
 
 template <typename R>
 __device__ __forceinline__ void cmac(R& pr, R& pi, R a, R b, const cplx<R>& v)
@@ -117,8 +128,8 @@ __device__ __forceinline__ void cmac(R& pr, R& pi, R a, R b, const cplx<R>& v)
     pi = fma(b, v.re, pi);
 }
 
-template <typename R, int RPT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RPT == 8 ? 4 : 1)))
+template <typename R, int RPT, int NC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(apply_waves(RPT, NC, sizeof(R)))))
 k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
                                                const QRec* __restrict__ rec, KLayout L,
                                                const cplx<R>* __restrict__ psi, cplx<R>* __restrict__ out)
@@ -127,7 +138,8 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
     constexpr uint32_t esz = sizeof(cplx<R>);
     // byte weights of the four gathered index bits: esz * 2^m
     constexpr uint32_t kDotW = (esz) | (2 * esz) << 8 | (4 * esz) << 16 | (8 * esz) << 24;
-    __shared__ ApplyLds<R, RPT> S;
+    __shared__ ApplyLds<R, RPT, NC> S;
+    constexpr uint32_t TS = RPT << kLaneBits;   // rows of a column's tile
     const char* src_b = reinterpret_cast<const char*>(S.src);
     const char* tab_b = reinterpret_cast<const char*>(S.tabs);
     auto src_at = [&](uint32_t off) { return *reinterpret_cast<const cplx<R>*>(src_b + off); };
@@ -137,11 +149,11 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
     const uint32_t nt = 1u << lb;
     const uint32_t tile = tile_of_block(blockIdx.x, L);
     const uint32_t tid = threadIdx.x;
-    const int rc = L.real[blockIdx.y];
+    const int rc = L.real[blockIdx.y * NC];   // the same for all NC columns
     const int M = T.M;
     const uint32_t base = tile << L.tile_bits;
-    psi += (uint64_t)(L.col0 + blockIdx.y) * L.dim;   // this workgroup's column
-    out += (uint64_t)(L.col0 + blockIdx.y) * L.dim;
+    psi += (uint64_t)(L.col0 + blockIdx.y * NC) * L.dim;   // this workgroup's first column
+    out += (uint64_t)(L.col0 + blockIdx.y * NC) * L.dim;
 
     // bits 0..3 and 4..7 of tid, one per byte
     uint32_t B0 = 0, B1 = 0;
@@ -155,13 +167,27 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
     // complex128 sums directly in pr/pi; complex64 sums each chunk in FP32 and
     // carries the running total in FP64.
     constexpr bool kSplit = sizeof(R) < sizeof(double);
-    double acc_re[RPT], acc_im[RPT];
-    R pr[RPT], pi[RPT];
+    double acc_re[NC][RPT], acc_im[NC][RPT];
+    R pr[NC][RPT], pi[NC][RPT];
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        acc_re[k] = acc_im[k] = 0.0;
-        pr[k] = pi[k] = R(0);
-    }
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            acc_re[c][k] = acc_im[c][k] = 0.0;
+            pr[c][k] = pi[c][k] = R(0);
+        }
+    auto carry = [&]() {   // complex64: chunk sums into the FP64 running totals
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) {
+                acc_re[c][k] += (double)pr[c][k];
+                acc_im[c][k] += (double)pi[c][k];
+                pr[c][k] = pi[c][k] = R(0);
+            }
+    };
+    // column c's source row at byte offset off of its tile
+    auto src_row = [&](int c, uint32_t off) { return src_at(off + (uint32_t)c * TS * esz); };
 
     for (int g = 0; g < L.n_chunks; ++g) {
         const QApplyChunk C = chunks[g];
@@ -172,7 +198,10 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
         if (C.new_tile) {
             const uint64_t sbase = (uint64_t)(tile ^ C.x_high) << L.tile_bits;
 #pragma unroll
-            for (int k = 0; k < RPT; ++k) S.src[tid + k * nt] = psi[sbase + tid + k * nt];
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int k = 0; k < RPT; ++k)
+                    S.src[c * TS + tid + k * nt] = (psi + c * L.dim)[sbase + tid + k * nt];
         }
         // Staged QUAD table entry i of slot j: sign_tile * T[i ^ index_tile].
         for (uint32_t e = tid; e < C.n_quad * 16; e += nt) {
@@ -233,7 +262,7 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
                         for (int e = 0; e < NE; ++e)
                             t[e] = tab_at(ia + (uint32_t)e * kof + j * 16u * esz);
                     };
-                    auto member_fma = [&](auto jc, cplx<R> (&t)[NE], const cplx<R> (&v)[RPT]) {
+                    auto member_fma = [&](auto jc, cplx<R> (&t)[NE], const cplx<R> (&v)[NC][RPT]) {
                         constexpr int j = decltype(jc)::value;
                         constexpr int XK = group_xk(J, j), ZK = group_zk(XK, P);
 #pragma unroll
@@ -242,12 +271,14 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
                             t[e].im = flip31(t[e].im, sl);
                         }
 #pragma unroll
-                        for (int k = 0; k < RPT; ++k) {
-                            const cplx<R> te = t[pack_bits3(k & XK, XK)];
-                            const bool neg = (popc3(k & ZK) & 1) != 0;
-                            const R a = neg ? -te.re : te.re, b = neg ? -te.im : te.im;
-                            cmac(pr[k], pi[k], a, b, v[k ^ XK]);
-                        }
+                        for (int c = 0; c < NC; ++c)
+#pragma unroll
+                            for (int k = 0; k < RPT; ++k) {
+                                const cplx<R> te = t[pack_bits3(k & XK, XK)];
+                                const bool neg = (popc3(k & ZK) & 1) != 0;
+                                const R a = neg ? -te.re : te.re, b = neg ? -te.im : te.im;
+                                cmac(pr[c][k], pi[c][k], a, b, v[c][k ^ XK]);
+                            }
                     };
                     using I0 = std::integral_constant<int, 0>;
                     using I1 = std::integral_constant<int, 1>;
@@ -256,9 +287,11 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
                     load_member(I0{}, ta);
                     __builtin_amdgcn_sched_barrier(0);
                     const uint32_t sb = tid_b ^ q.xoff;
-                    cplx<R> v[RPT];
+                    cplx<R> v[NC][RPT];
 #pragma unroll
-                    for (int k = 0; k < RPT; ++k) v[k] = src_at(sb + ((uint32_t)k << kLaneBits) * esz);
+                    for (int c = 0; c < NC; ++c)
+#pragma unroll
+                        for (int k = 0; k < RPT; ++k) v[c][k] = src_row(c, sb + ((uint32_t)k << kLaneBits) * esz);
                     __builtin_amdgcn_sched_barrier(0);
                     if constexpr (J == 1) {
                         load_member(I1{}, tb);
@@ -311,9 +344,11 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
                 // that each row's FMAs wait only for its own load
                 __builtin_amdgcn_sched_barrier(0);
                 const uint32_t sb = tid_b ^ q.xoff;
-                cplx<R> v[RPT];
+                cplx<R> v[NC][RPT];
 #pragma unroll
-                for (int k = 0; k < RPT; ++k) v[k] = src_at(sb + (((uint32_t)k ^ XK) << kLaneBits) * esz);
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) v[c][k] = src_row(c, sb + (((uint32_t)k ^ XK) << kLaneBits) * esz);
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int p = 0; p < RPT; ++p) {
@@ -322,12 +357,14 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
                     te[p].im = flip31(te[p].im, sl);
                 }
 #pragma unroll
-                for (int k = 0; k < RPT; ++k) {
-                    const cplx<R> t = te[k & (int)XK];
-                    const bool neg = (__builtin_popcount((uint32_t)k & ZK) & 1) != 0;
-                    const R a = neg ? -t.re : t.re, b = neg ? -t.im : t.im;
-                    cmac(pr[k], pi[k], a, b, v[k]);
-                }
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) {
+                        const cplx<R> t = te[k & (int)XK];
+                        const bool neg = (__builtin_popcount((uint32_t)k & ZK) & 1) != 0;
+                        const R a = neg ? -t.re : t.re, b = neg ? -t.im : t.im;
+                        cmac(pr[c][k], pi[c][k], a, b, v[c][k]);
+                    }
                 if constexpr (!kEarlyRecord) {
                     __builtin_amdgcn_sched_barrier(0);
                     qn = rec[mi + 1];
@@ -395,11 +432,13 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
                 }
                 const uint32_t sb = tid_b ^ q.xoff;
 #pragma unroll
-                for (int k = 0; k < RPT; ++k) {
-                    const bool neg = (__builtin_popcount((uint32_t)k & (uint32_t)ZK) & 1) != 0;
-                    const cplx<R> v = src_at(sb + ((uint32_t)k << kLaneBits) * esz);
-                    cmac(pr[k], pi[k], neg ? -X[k].re : X[k].re, neg ? -X[k].im : X[k].im, v);
-                }
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) {
+                        const bool neg = (__builtin_popcount((uint32_t)k & (uint32_t)ZK) & 1) != 0;
+                        const cplx<R> v = src_row(c, sb + ((uint32_t)k << kLaneBits) * esz);
+                        cmac(pr[c][k], pi[c][k], neg ? -X[k].re : X[k].re, neg ? -X[k].im : X[k].im, v);
+                    }
             }
         };
         if (RPT > 1) {
@@ -428,8 +467,11 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
                 const R a3 = flip(l[3] + tk[k * 4 + 3], sa ^ sbb);
                 const R dre = flip(ph[0].re * a0 + ph[1].re * a1 + ph[2].re * a2 + ph[3].re * a3, s);
                 const R dim = flip(ph[0].im * a0 + ph[1].im * a1 + ph[2].im * a2 + ph[3].im * a3, s);
-                const cplx<R> v = src_at(sb + (((uint32_t)k ^ q.koffs) << lb) * esz);
-                cmac(pr[k], pi[k], dre, dim, v);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const cplx<R> v = src_row(c, sb + (((uint32_t)k ^ q.koffs) << lb) * esz);
+                    cmac(pr[c][k], pi[c][k], dre, dim, v);
+                }
             }
         }
         // DIAG (source = own row): the precomputed diagonal of H
@@ -438,71 +480,63 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
 #pragma unroll
             for (int k = 0; k < RPT; ++k) {
                 const R d = (R)dg[(uint32_t)k << lb];
-                const cplx<R> v = src_at(tid_b + ((uint32_t)k << lb) * esz);
-                pr[k] = fma(d, v.re, pr[k]);
-                pi[k] = fma(d, v.im, pi[k]);
-            }
-        }
-        if (kSplit) {
 #pragma unroll
-            for (int k = 0; k < RPT; ++k) {
-                acc_re[k] += (double)pr[k];
-                acc_im[k] += (double)pi[k];
-                pr[k] = pi[k] = R(0);
+                for (int c = 0; c < NC; ++c) {
+                    const cplx<R> v = src_row(c, tid_b + ((uint32_t)k << lb) * esz);
+                    pr[c][k] = fma(d, v.re, pr[c][k]);
+                    pi[c][k] = fma(d, v.im, pi[c][k]);
+                }
             }
         }
+        if (kSplit) carry();
     }
 
     // QUAD masks that flip only tile bits: D_x is one number per tile, the
     // source rows are the same rows of tile ^ x_high.  Streamed straight from
     // global memory with the next mask's rows loaded one mask ahead.
     if (L.n_far > 0) {
-        cplx<R> vn[RPT];
+        cplx<R> vn[NC][RPT];
         FarRec fn = L.far[0];
         const cplx<R>* sp = psi + ((uint64_t)(tile ^ fn.x_high) << L.tile_bits);
 #pragma unroll
-        for (int k = 0; k < RPT; ++k) vn[k] = sp[tid + k * nt];
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) vn[c][k] = (sp + c * L.dim)[tid + k * nt];
         for (int f = 0; f < L.n_far; ++f) {
             const FarRec fc = fn;
-            cplx<R> v[RPT];
+            cplx<R> v[NC][RPT];
 #pragma unroll
-            for (int k = 0; k < RPT; ++k) v[k] = vn[k];
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) v[c][k] = vn[c][k];
             if (f + 1 < L.n_far) {
                 fn = L.far[f + 1];
                 sp = psi + ((uint64_t)(tile ^ fn.x_high) << L.tile_bits);
 #pragma unroll
-                for (int k = 0; k < RPT; ++k) vn[k] = sp[tid + k * nt];
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) vn[c][k] = (sp + c * L.dim)[tid + k * nt];
             }
             const cplx<R> t = T.tab4[((size_t)fc.tab * T.n_real + rc) * 16 + quad_index(base, fc.qpack)];
             const uint32_t s = parity(base & fc.zbase);
             const R tr = flip(t.re, s), ti = flip(t.im, s);
 #pragma unroll
-            for (int k = 0; k < RPT; ++k) cmac(pr[k], pi[k], tr, ti, v[k]);
-            if (kSplit && (f & 63) == 63) {
+            for (int c = 0; c < NC; ++c)
 #pragma unroll
-                for (int k = 0; k < RPT; ++k) {
-                    acc_re[k] += (double)pr[k];
-                    acc_im[k] += (double)pi[k];
-                    pr[k] = pi[k] = R(0);
-                }
-            }
+                for (int k = 0; k < RPT; ++k) cmac(pr[c][k], pi[c][k], tr, ti, v[c][k]);
+            if (kSplit && (f & 63) == 63) carry();
         }
-        if (kSplit) {
-#pragma unroll
-            for (int k = 0; k < RPT; ++k) {
-                acc_re[k] += (double)pr[k];
-                acc_im[k] += (double)pi[k];
-                pr[k] = pi[k] = R(0);
-            }
-        }
+        if (kSplit) carry();
     }
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        cplx<R> o;
-        o.re = kSplit ? (R)acc_re[k] : pr[k];
-        o.im = kSplit ? (R)acc_im[k] : pi[k];
-        out[(uint64_t)base + tid + k * nt] = o;
-    }
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            cplx<R> o;
+            o.re = kSplit ? (R)acc_re[c][k] : pr[c][k];
+            o.im = kSplit ? (R)acc_im[c][k] : pi[c][k];
+            (out + c * L.dim)[(uint64_t)base + tid + k * nt] = o;
+        }
 }
 
 // dst = transpose of src viewed as a [2^log_h] x [2^log_w] matrix (row-major),
@@ -587,17 +621,28 @@ namespace {
 
 template <typename R>
 void launch_t(const ApplyPlan& P, const KTerms<R>& T, const QApplyChunk* chunks, const QRec* rec, KLayout L,
-              int ncols, const void* psi, void* out, hipStream_t s)
+              int ncols, int nc, const void* psi, void* out, hipStream_t s)
 {
-    dim3 grid(L.n_tiles, ncols), block(P.nt);
     auto* in = static_cast<const cplx<R>*>(psi);
     auto* o = static_cast<cplx<R>*>(out);
-    switch (P.rpt) {
-    case 1: hipLaunchKernelGGL((k_apply<R, 1>), grid, block, 0, s, T, chunks, rec, L, in, o); break;
-    case 2: hipLaunchKernelGGL((k_apply<R, 2>), grid, block, 0, s, T, chunks, rec, L, in, o); break;
-    case 4: hipLaunchKernelGGL((k_apply<R, 4>), grid, block, 0, s, T, chunks, rec, L, in, o); break;
-    case 8: hipLaunchKernelGGL((k_apply<R, 8>), grid, block, 0, s, T, chunks, rec, L, in, o); break;
-    default: throw Error(SYK_EINVAL, "apply_H: unsupported rows per thread");
+    if (nc == 2) {
+        // the caller has checked that the columns pair up by realisation
+        if (ncols % 2 != 0) throw Error(SYK_EINVAL, "apply_H: odd column count for two columns per workgroup");
+        dim3 grid(L.n_tiles, ncols / 2), block(P.nt);
+        switch (P.rpt) {
+        case 4: hipLaunchKernelGGL((k_apply<R, 4, 2>), grid, block, 0, s, T, chunks, rec, L, in, o); break;
+        case 8: hipLaunchKernelGGL((k_apply<R, 8, 2>), grid, block, 0, s, T, chunks, rec, L, in, o); break;
+        default: throw Error(SYK_EINVAL, "apply_H: two columns per workgroup need 4 or 8 rows per thread");
+        }
+    } else {
+        dim3 grid(L.n_tiles, ncols), block(P.nt);
+        switch (P.rpt) {
+        case 1: hipLaunchKernelGGL((k_apply<R, 1, 1>), grid, block, 0, s, T, chunks, rec, L, in, o); break;
+        case 2: hipLaunchKernelGGL((k_apply<R, 2, 1>), grid, block, 0, s, T, chunks, rec, L, in, o); break;
+        case 4: hipLaunchKernelGGL((k_apply<R, 4, 1>), grid, block, 0, s, T, chunks, rec, L, in, o); break;
+        case 8: hipLaunchKernelGGL((k_apply<R, 8, 1>), grid, block, 0, s, T, chunks, rec, L, in, o); break;
+        default: throw Error(SYK_EINVAL, "apply_H: unsupported rows per thread");
+        }
     }
     SYK_HIP(hipGetLastError());
 }
@@ -899,7 +944,6 @@ const HamiltonianDev::ApplyTables& apply_tables_for(const HamiltonianDev& H, con
 
 ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune)
 {
-    (void)dtype;
     ApplyPlan P{};
     P.slices = (nvec + kColsPerLaunch - 1) / kColsPerLaunch;
     // 2048-row source tiles (256 threads, 8 rows each); smaller tiles when the
@@ -914,6 +958,18 @@ ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune)
     P.nt = 1 << P.lb;
     P.rpt = 1 << (tb - P.lb);
     P.xcd_remap = tune ? tune->xcd_remap : 1;
+    // Two columns of one realisation per workgroup (where a launch's columns
+    // pair up) need a whole 256-thread workgroup with at least 4 rows per
+    // thread.  By default complex64 takes them: its 8-row kernel holds both
+    // columns' sums at three waves per SIMD and decodes each mask once for
+    // both; complex128 would drop to two waves per SIMD and gains nothing.
+    const bool explicit_cols = tune && tune->cols > 0;
+    P.nc = explicit_cols ? tune->cols : (dtype == SYK_C64 ? 2 : 1);
+    if (P.nc == 2 && P.rpt < 4) {
+        if (explicit_cols && tune->tile_bits > 0)
+            throw Error(SYK_EINVAL, "apply_H: two columns per workgroup need tile_bits >= 10");
+        P.nc = 1;
+    }
     // QUAD masks whose four qubits all lie above the tile would each stream a
     // whole tile from global memory; with at least C(7,4) of them, run the
     // masks that sit better in the rotated layout there.
@@ -994,6 +1050,7 @@ void launch_apply_impl(const HamiltonianDev& H, syk_dtype dtype, int nvec, const
 {
     const int M = H.M;
     if (P.lb > kLaneBits || (P.rpt > 1 && P.lb != kLaneBits) || P.nt != (1 << P.lb) ||
+        (P.nc != 1 && (P.nc != 2 || P.rpt < 4)) ||
         (P.rpt << P.lb) != (1 << P.tile_bits) || P.tile_bits > M ||
         (P.two_layouts && (P.tile_bits < 5 || M - P.tile_bits < 5)))
         throw Error(SYK_EINVAL, "apply_H: inconsistent launch shape");
@@ -1014,6 +1071,11 @@ void launch_apply_impl(const HamiltonianDev& H, syk_dtype dtype, int nvec, const
         const int col0 = sl * kColsPerLaunch;
         const int ncols = std::min(kColsPerLaunch, nvec - col0);
         for (int c = 0; c < ncols; ++c) L.real[c] = real_of_col ? real_of_col[col0 + c] : 0;
+        // two columns per workgroup only where every pair of the slice shares its realisation
+        int nc = P.nc;
+        if (nc == 2 && ncols % 2 != 0) nc = 1;
+        for (int c = 0; nc == 2 && c < ncols; c += 2)
+            if (L.real[c] != L.real[c + 1]) nc = 1;
         const char* in_c = static_cast<const char*>(psi) + (size_t)col0 * dim * esz;
         char* out_c = static_cast<char*>(out) + (size_t)col0 * dim * esz;
         auto run = [&](const HamiltonianDev::ApplyTables& Tb, const void* src, void* dst) {
@@ -1024,10 +1086,10 @@ void launch_apply_impl(const HamiltonianDev& H, syk_dtype dtype, int nvec, const
             const auto* rc = Tb.recs.as<QRec>();
             if (dtype == SYK_C128) {
                 KTerms<double> T{H.tab4_d, H.qinfo, H.phi2_d, H.w2_d, H.diag.as<double>(), H.n_real, M};
-                launch_t<double>(P, T, ch, rc, L, ncols, src, dst, s);
+                launch_t<double>(P, T, ch, rc, L, ncols, nc, src, dst, s);
             } else {
                 KTerms<float> T{H.tab4_f, H.qinfo, H.phi2_f, H.w2_f, H.diag.as<double>(), H.n_real, M};
-                launch_t<float>(P, T, ch, rc, L, ncols, src, dst, s);
+                launch_t<float>(P, T, ch, rc, L, ncols, nc, src, dst, s);
             }
         };
         if (B) {

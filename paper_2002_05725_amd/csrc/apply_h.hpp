@@ -59,6 +59,7 @@ static_assert(sizeof(QApplyChunk) == 64, "QApplyChunk layout");
 struct ApplyTuning {
     int tile_bits;
     int xcd_remap;
+    int cols;        // columns per workgroup (1 or 2; 0 = default)
 };
 
 constexpr int kColsPerLaunch = 64;   // columns of a block served by one launch
@@ -71,6 +72,7 @@ struct ApplyPlan {
     int rpt;         // tile rows per thread
     int xcd_remap;
     int two_layouts; // also run the masks that flip few rows of a tile on a bit-rotated copy
+    int nc;          // columns per workgroup where a launch's columns pair up by realisation (1 or 2)
 };
 
 ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune);
@@ -79,7 +81,7 @@ ApplyPlan plan_apply(int M, int nvec, syk_dtype dtype, const ApplyTuning* tune);
 // syk_set_apply_tuning settings.
 inline ApplyPlan plan_for(const syk_terms_s& h, int M, int nvec, syk_dtype dtype)
 {
-    ApplyTuning t{h.tune_tile_bits, h.tune_xcd};
+    ApplyTuning t{h.tune_tile_bits, h.tune_xcd, h.tune_cols};
     return plan_apply(M, nvec, dtype, h.tuned ? &t : nullptr);
 }
 inline ApplyPlan plan_for(const syk_terms_s& h, int nvec, syk_dtype dtype) { return plan_for(h, h.H.M, nvec, dtype); }

@@ -94,7 +94,7 @@ struct syk_terms_s {
     };
     std::unique_ptr<Sector> sectors[2];
     bool tuned = false;             // apply_H launch shape set by syk_set_apply_tuning
-    int tune_tile_bits = 0, tune_xcd = 1;
+    int tune_tile_bits = 0, tune_xcd = 1, tune_cols = 0;
 };
 
 namespace syk {

@@ -9,12 +9,19 @@ from paper_2002_05725_amd import autotune
 
 
 def test_candidates_cover_valid_tiles():
-    assert autotune.candidates(52) == [(tb, x) for tb in (8, 9, 10, 11) for x in (1, 0)]
-    assert autotune.candidates(18) == [(8, 1), (8, 0), (9, 1), (9, 0)]
-    assert autotune.candidates(8) == [(4, 1), (4, 0)]
+    assert autotune.candidates(52) == [(tb, x, 1) for tb in (8, 9, 10, 11) for x in (1, 0)]
+    assert autotune.candidates(18) == [(8, 1, 1), (8, 0, 1), (9, 1, 1), (9, 0, 1)]
+    assert autotune.candidates(8) == [(4, 1, 1), (4, 0, 1)]
+    # two columns per workgroup: even blocks, tiles of 2^10 and 2^11 rows only
+    assert autotune.candidates(52, 64) == autotune.candidates(52) + [(10, 1, 2), (10, 0, 2), (11, 1, 2), (11, 0, 2)]
+    assert autotune.candidates(52, 3) == autotune.candidates(52)
+    assert autotune.candidates(18, 64) == autotune.candidates(18)
+    assert autotune.candidates(20, 2) == autotune.candidates(20) + [(10, 1, 2), (10, 0, 2)]
     for N in (8, 12, 18, 24, 52, 60):
-        for tb, x in autotune.candidates(N):
-            assert tb <= N // 2 and tb <= 11 and x in (0, 1)
+        for nvec in (1, 2, 5, 64):
+            for tb, x, nc in autotune.candidates(N, nvec):
+                assert tb <= N // 2 and tb <= 11 and x in (0, 1) and nc in (1, 2)
+                assert nc == 1 or (tb >= 10 and nvec % 2 == 0)
 
 
 def test_cache_key_separates_every_field():

@@ -30,8 +30,8 @@ def test_every_candidate_shape_matches_checker(N):
         rows = np.unique(np.concatenate([inputs.row_sample(N, 23, 2048), [0, 255, 256, 2047, 2048, psi.size - 1]]))
         ref = native.apply_rows(N, J, psi, rows)
     idx = torch.from_numpy(rows).to(DEV)
-    for tb, xr in autotune.candidates(N):
-        api.set_apply_tuning(T, tb, xr)
+    for tb, xr, _ in autotune.candidates(N):
+        api.set_apply_tuning(T, tb, xr, 1)
         for dt, tol in ((torch.complex128, 1e-12), (torch.complex64, 2e-6)):
             print(f"N={N} tile_bits={tb} xcd_remap={xr} {dt}", flush=True)
             y = api.apply_H(T, torch.from_numpy(psi).to(DEV).to(dt))
@@ -45,7 +45,7 @@ def test_tune_installs_fastest_and_caches(tmp_path):
     T = api.Terms(N, inputs.couplings(N, 0))
     cache = str(tmp_path / "tune.json")
     best = autotune.tune_apply(T, torch.complex64, nvec=4, reps=2, cache=cache)
-    assert len(best["timed"]) == len(autotune.candidates(N))
+    assert len(best["timed"]) == len(autotune.candidates(N, 4))
     assert best["ms"] == min(r["ms"] for r in best["timed"]) and best["ms"] > 0
     # the installed shape gives the same product as the default one
     x = torch.from_numpy(np.stack([inputs.typical_state(N, s) for s in range(4)])).to(DEV).to(torch.complex64)
@@ -56,5 +56,6 @@ def test_tune_installs_fastest_and_caches(tmp_path):
     # a second call installs the cached entry without timing
     again = autotune.tune_apply(T, torch.complex64, nvec=4, reps=2, cache=cache)
     assert again == autotune.read_cache(cache)[autotune.cache_key(autotune._arch(), N, torch.complex64, 4)]
-    assert (again["tile_bits"], again["xcd_remap"]) == (best["tile_bits"], best["xcd_remap"])
+    assert ((again["tile_bits"], again["xcd_remap"], again["cols_per_group"]) ==
+            (best["tile_bits"], best["xcd_remap"], best["cols_per_group"]))
     T.close()
