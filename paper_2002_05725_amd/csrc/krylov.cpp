@@ -2,9 +2,14 @@
 // ||psi|| V e^{zT} e_1, with V an orthonormal basis of span{psi, H psi, ...}
 // (m vectors) and T = V^dag H V the m x m tridiagonal projection.  The basis
 // is orthogonalised against all previous vectors with two passes of classical
-// Gram-Schmidt; inner products are FP64 on the device, T and its exponential
-// are FP64 on the host.
+// Gram-Schmidt; inner products are FP64 on the device, T (tridiagonal QR for
+// its eigen-decomposition) and its exponential are FP64 on the host.  Up to 16 basis vectors the first pass's update and
+// the second pass's projection share one sweep over the basis.  The
+// projections, alpha, beta and the invariant-subspace test stay on the device
+// for the whole build (no host round trip per iteration); the host reads them
+// once at the end.
 #include "krylov.hpp"
+#include "tridiag_eig.hpp"
 
 #include <algorithm>
 
@@ -30,50 +35,6 @@ void BlockCtx::majorana(int a, int s_in, const void* in, void* out)
 {
     if (s_in < 0) ops.majorana(a, in, out);
     else ops.majorana_sector(a, Hact->M, s_in, in, out);
-}
-
-// Cyclic Jacobi rotations on the dense n x n matrix (O(n^3) per sweep, a few
-// sweeps).  Converges to full FP64 accuracy.
-void symmetric_eig(int n, std::vector<double>& a, std::vector<double>& w, std::vector<double>& v)
-{
-    v.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) v[(size_t)i * n + i] = 1.0;
-    for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) {
-                double x = a[(size_t)i * n + j] * a[(size_t)i * n + j];
-                tot += x;
-                if (i != j) off += x;
-            }
-        if (off <= 1e-34 * tot || off == 0.0) break;
-        for (int p = 0; p < n - 1; ++p)
-            for (int q = p + 1; q < n; ++q) {
-                const double apq = a[(size_t)p * n + q];
-                if (apq == 0.0) continue;
-                const double app = a[(size_t)p * n + p], aqq = a[(size_t)q * n + q];
-                const double theta = (aqq - app) / (2.0 * apq);
-                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-                const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
-                for (int k = 0; k < n; ++k) {   // columns p, q
-                    const double akp = a[(size_t)k * n + p], akq = a[(size_t)k * n + q];
-                    a[(size_t)k * n + p] = cs * akp - sn * akq;
-                    a[(size_t)k * n + q] = sn * akp + cs * akq;
-                }
-                for (int k = 0; k < n; ++k) {   // rows p, q
-                    const double apk = a[(size_t)p * n + k], aqk = a[(size_t)q * n + k];
-                    a[(size_t)p * n + k] = cs * apk - sn * aqk;
-                    a[(size_t)q * n + k] = sn * apk + cs * aqk;
-                }
-                for (int k = 0; k < n; ++k) {
-                    const double vkp = v[(size_t)k * n + p], vkq = v[(size_t)k * n + q];
-                    v[(size_t)k * n + p] = cs * vkp - sn * vkq;
-                    v[(size_t)k * n + q] = sn * vkp + cs * vkq;
-                }
-            }
-    }
-    w.resize(n);
-    for (int i = 0; i < n; ++i) w[i] = a[(size_t)i * n + i];
 }
 
 // Builds the Krylov basis of psi (V, m vectors in the workspace) and the
@@ -102,47 +63,62 @@ LanczosBasis lanczos_build(BlockCtx& c, const void* psi, int m)
     L.alpha.assign((size_t)m * B, 0.0);
     L.beta.assign((size_t)m * B, 0.0);
     L.kdim.assign(B, m);
-    std::vector<double>& alpha = L.alpha;
-    std::vector<double>& beta = L.beta;
-    std::vector<int>& kdim = L.kdim;
-    std::vector<double> scale(B, 0.0);
+    // Device scalars: alpha, beta [m][B], then scale, nrm, f [B]; kdim [B] and
+    // the error flag.  A column whose subspace became invariant keeps f = 0,
+    // so its later basis vectors are zero.
+    const size_t nB = (size_t)B;
+    double* dd = (double*)c.h.ws.get("lz_dbl", (2 * (size_t)m + 3) * nB * sizeof(double));
+    int* di = (int*)c.h.ws.get("lz_int", (nB + 1) * sizeof(int));
+    {
+        std::vector<double> h((2 * (size_t)m + 3) * nB, 0.0);
+        std::copy(L.nrm.begin(), L.nrm.end(), h.begin() + (2 * (size_t)m + 1) * nB);
+        ops.to_device(dd, h.data(), h.size() * sizeof(double));
+        std::vector<int> hi(nB + 1, m);
+        hi[nB] = 0;
+        ops.to_device(di, hi.data(), hi.size() * sizeof(int));
+    }
+    LanczosScalars z{dd, dd + (size_t)m * nB, di, dd + 2 * (size_t)m * nB, dd + (2 * (size_t)m + 1) * nB,
+                     dd + (2 * (size_t)m + 2) * nB, di + nB};
+    // projections of up to m basis vectors (sized once: no reallocation inside the loop)
+    const size_t proj_bytes = (size_t)std::max(m, VecOps::kFusedMax) * nB * 2 * sizeof(double);
+    c.h.ws.get("gs_c1", proj_bytes);
+    c.h.ws.get("gs_c2", proj_bytes);
     for (int j = 0; j < m; ++j) {
         c.apply_H(V + (size_t)j * vb, w);
-        std::vector<zd> c1 = ops.multidot(V, j + 1, w);
-        ops.update(w, V, j + 1, c1, false);
-        std::vector<zd> c2 = ops.multidot(V, j + 1, w);
-        std::vector<double> b2 = ops.update(w, V, j + 1, c2, true);
-        std::vector<double> f(B, 0.0);
-        for (int b = 0; b < B; ++b) {
-            const double a = (c1[(size_t)j * B + b] + c2[(size_t)j * B + b]).real();
-            const double bt = std::sqrt(b2[b]);
-            if (!std::isfinite(a) || !std::isfinite(bt)) throw Error(SYK_EBREAKDOWN, "non-finite Lanczos coefficient");
-            alpha[(size_t)j * B + b] = a;
-            beta[(size_t)j * B + b] = bt;
-            if (j >= kdim[b]) continue;   // column already invariant: its basis stays zero
-            scale[b] = std::max(scale[b], std::fabs(a) + (j > 0 ? beta[(size_t)(j - 1) * B + b] : 0.0));
-            if (j < m - 1) {
-                if (bt <= 1e-13 * scale[b] || L.nrm[b] == 0.0) {
-                    kdim[b] = j + 1;          // invariant subspace: T is exact
-                } else {
-                    f[b] = 1.0 / bt;
-                }
-            }
+        const double* d1 = ops.multidot_dev(V, j + 1, w, "gs_c1");
+        const double* d2;
+        if (j + 1 <= VecOps::kFusedMax) {
+            d2 = ops.update_dot(w, V, j + 1, d1, "gs_c2");
+        } else {
+            ops.update_dev_norm(w, V, j + 1, d1, false);
+            d2 = ops.multidot_dev(V, j + 1, w, "gs_c2");
         }
-        if (j < m - 1) ops.scale(V + (size_t)(j + 1) * vb, w, f);
+        const double* wn = ops.update_dev_norm(w, V, j + 1, d2, true);
+        ops.lanczos_coef(d1, d2, wn, j, m, z);
+        if (j < m - 1) ops.scale_dev(V + (size_t)(j + 1) * vb, w, z.f);
     }
+    ops.to_host(L.alpha.data(), z.alpha, L.alpha.size() * sizeof(double));
+    ops.to_host(L.beta.data(), z.beta, L.beta.size() * sizeof(double));
+    std::vector<int> hi(nB + 1);
+    ops.to_host(hi.data(), di, hi.size() * sizeof(int));
+    if (hi[nB] != 0) throw Error(SYK_EBREAKDOWN, "non-finite Lanczos coefficient");
+    std::copy(hi.begin(), hi.begin() + nB, L.kdim.begin());
     return L;
 }
 
 void ritz_values(const LanczosBasis& L, int col, int nvec, std::vector<double>& ev, std::vector<double>& S)
 {
     const int k = L.kdim[col];
-    std::vector<double> T((size_t)k * k, 0.0);
+    std::vector<double> d(k), e(k > 1 ? k - 1 : 0);
     for (int i = 0; i < k; ++i) {
-        T[(size_t)i * k + i] = L.alpha[(size_t)i * nvec + col];
-        if (i + 1 < k) T[(size_t)i * k + i + 1] = T[(size_t)(i + 1) * k + i] = L.beta[(size_t)i * nvec + col];
+        d[i] = L.alpha[(size_t)i * nvec + col];
+        if (i + 1 < k) e[i] = L.beta[(size_t)i * nvec + col];
     }
-    symmetric_eig(k, T, ev, S);
+    try {
+        tridiag_eig(k, d, e, ev, S);
+    } catch (const std::runtime_error& x) {
+        throw Error(SYK_EBREAKDOWN, x.what());
+    }
 }
 
 void krylov_step(BlockCtx& c, void* psi, std::complex<double> z, int m, KrylovStats& st)

@@ -39,10 +39,6 @@ struct KrylovStats {
     int steps = 0;
 };
 
-// Eigen-decomposition of a real symmetric n x n matrix (row-major a, destroyed):
-// eigenvalues in w, eigenvectors as columns of v (row-major n x n).
-void symmetric_eig(int n, std::vector<double>& a, std::vector<double>& w, std::vector<double>& v);
-
 // Lanczos basis of one step: V (m vectors of the block, workspace), the
 // tridiagonal T per column (alpha: diagonal, beta: off-diagonal, [m][nvec]),
 // the Krylov dimension per column (< m after an invariant subspace) and ||psi||.

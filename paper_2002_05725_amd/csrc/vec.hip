@@ -3,11 +3,13 @@
 //
 // Grid (gx, nvec): workgroup (bx, c) strides over the rows of column c, so
 // loads are coalesced and every column reduces on its own.  Reductions
-// accumulate in FP64 per thread, reduce over the workgroup with a fixed-shape
-// tree in LDS, then over the fixed number of workgroups in index order: the
-// result does not depend on timing.
+// accumulate in FP64 per thread, reduce over each wave with a fixed butterfly
+// of lane exchanges, over the four waves of the workgroup in wave order, then
+// over the fixed number of workgroups in index order: the result does not
+// depend on timing.
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "vec.hpp"
 
@@ -17,6 +19,7 @@ namespace {
 
 constexpr int RB = 256;    // threads per workgroup
 constexpr int KC = 8;      // vectors per pass of a multi-vector kernel
+constexpr int kWaves = RB / 64;
 
 struct Shape {
     int64_t D;   // rows per column
@@ -37,15 +40,27 @@ inline dim3 grid_of(const Shape& S, bool reduction)
     return dim3(gx, S.B);
 }
 
-// Sum red[i][*] over the workgroup (fixed tree); thread 0 holds the totals.
-__device__ __forceinline__ void tree_reduce(double* red, int n)
+// Workgroup sums of a[0..n) (n <= N, the same n on every thread): each wave
+// adds its 64 lanes with a butterfly of lane exchanges, lane 0 of every wave
+// stores its sums in red[wave][i], and after one barrier thread i < n returns
+// red[0][i] + red[1][i] + red[2][i] + red[3][i] (others return 0).  red holds
+// kWaves * N doubles.
+template <int N>
+__device__ __forceinline__ double block_sum(double (&a)[N], int n, double* red)
 {
-    __syncthreads();
-    for (int s = RB / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int i = 0; i < n; ++i) red[i * RB + threadIdx.x] += red[i * RB + threadIdx.x + s];
-        __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        if (i >= n) break;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) a[i] += __shfl_xor(a[i], off, 64);
+        if (lane == 0) red[wave * N + i] = a[i];
     }
+    __syncthreads();
+    double s = 0.0;
+    if ((int)threadIdx.x < n)
+        for (int w = 0; w < kWaves; ++w) s += red[w * N + threadIdx.x];
+    return s;
 }
 
 template <typename R>
@@ -109,73 +124,81 @@ __global__ void __launch_bounds__(RB) k_majorana_sector(const cplx<R>* __restric
     }
 }
 
+// The multi-vector kernels take the number of basis vectors K as a template
+// argument: every load of a row is then unconditional and issued before the
+// first is used, instead of one branch and one wait per vector.
+template <int N, typename F>
+void with_count(int k, F&& f)
+{
+    if constexpr (N > 0) {
+        if (k == N) f(std::integral_constant<int, N>{});
+        else with_count<N - 1>(k, f);
+    } else {
+        throw Error(SYK_EINVAL, "vector kernels: unsupported number of basis vectors");
+    }
+}
+
 // partial[bx][k][c] = sum over this workgroup's rows of conj(V_k[r,c]) w[r,c]
-template <typename R>
-__global__ void __launch_bounds__(RB) k_multidot(const cplx<R>* __restrict__ V, int64_t vstride, int K,
+template <typename R, int K>
+__global__ void __launch_bounds__(RB) k_multidot(const cplx<R>* __restrict__ V, int64_t vstride,
                                                  const cplx<R>* __restrict__ w, Shape S,
                                                  double* __restrict__ partial)
 {
-    __shared__ double red[2 * KC * RB];
+    __shared__ double red[kWaves * 2 * K];
     const int64_t col = (int64_t)blockIdx.y * S.D;
-    double ar[KC], ai[KC];
+    double a[2 * K];
 #pragma unroll
-    for (int k = 0; k < KC; ++k) ar[k] = ai[k] = 0.0;
+    for (int k = 0; k < 2 * K; ++k) a[k] = 0.0;
     const int64_t step = (int64_t)gridDim.x * RB;
     for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < S.D; r += step) {
         const int64_t e = col + r;
         const cplx<R> b = w[e];
+        cplx<R> v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = V[k * vstride + e];
         const double br = b.re, bi = b.im;
 #pragma unroll
-        for (int k = 0; k < KC; ++k)
-            if (k < K) {
-                const cplx<R> v = V[k * vstride + e];
-                const double vr = v.re, vi = v.im;
-                ar[k] += vr * br + vi * bi;
-                ai[k] += vr * bi - vi * br;
-            }
-    }
-#pragma unroll
-    for (int k = 0; k < KC; ++k) {
-        red[(2 * k) * RB + threadIdx.x] = ar[k];
-        red[(2 * k + 1) * RB + threadIdx.x] = ai[k];
-    }
-    tree_reduce(red, 2 * K);
-    if (threadIdx.x == 0)
         for (int k = 0; k < K; ++k) {
-            double* p = partial + (((int64_t)blockIdx.x * K + k) * S.B + blockIdx.y) * 2;
-            p[0] = red[(2 * k) * RB];
-            p[1] = red[(2 * k + 1) * RB];
+            const double vr = v[k].re, vi = v[k].im;
+            a[2 * k] += vr * br + vi * bi;
+            a[2 * k + 1] += vr * bi - vi * br;
         }
+    }
+    const double t = block_sum(a, 2 * K, red);
+    // thread i < 2K holds (k, re/im) = (i / 2, i % 2)
+    if ((int)threadIdx.x < 2 * K)
+        partial[(((int64_t)blockIdx.x * K + (threadIdx.x >> 1)) * S.B + blockIdx.y) * 2 + (threadIdx.x & 1)] = t;
 }
 
 // w -= sum_k coef[k][c] V_k; optionally partial[bx][c] = sum |w_new|^2
-template <typename R>
+template <typename R, int K>
 __global__ void __launch_bounds__(RB) k_update(cplx<R>* __restrict__ w, const cplx<R>* __restrict__ V,
-                                               int64_t vstride, int K, const double* __restrict__ coef,
+                                               int64_t vstride, const double* __restrict__ coef,
                                                Shape S, double* __restrict__ partial)
 {
-    __shared__ double red[RB];
+    __shared__ double red[kWaves];
     const int c = blockIdx.y;
     const int64_t col = (int64_t)c * S.D;
-    double cr[KC], ci[KC];
+    double cr[K], ci[K];
 #pragma unroll
-    for (int k = 0; k < KC; ++k) {
-        cr[k] = (k < K) ? coef[(k * S.B + c) * 2] : 0.0;
-        ci[k] = (k < K) ? coef[(k * S.B + c) * 2 + 1] : 0.0;
+    for (int k = 0; k < K; ++k) {
+        cr[k] = coef[(k * S.B + c) * 2];
+        ci[k] = coef[(k * S.B + c) * 2 + 1];
     }
     double nrm = 0.0;
     const int64_t step = (int64_t)gridDim.x * RB;
     for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < S.D; r += step) {
         const int64_t e = col + r;
         const cplx<R> b = w[e];
+        cplx<R> v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = V[k * vstride + e];
         double xr = b.re, xi = b.im;
 #pragma unroll
-        for (int k = 0; k < KC; ++k)
-            if (k < K) {
-                const cplx<R> v = V[k * vstride + e];
-                xr -= cr[k] * v.re - ci[k] * v.im;
-                xi -= cr[k] * v.im + ci[k] * v.re;
-            }
+        for (int k = 0; k < K; ++k) {
+            xr -= cr[k] * v[k].re - ci[k] * v[k].im;
+            xi -= cr[k] * v[k].im + ci[k] * v[k].re;
+        }
         cplx<R> o;
         o.re = (R)xr;
         o.im = (R)xi;
@@ -184,9 +207,89 @@ __global__ void __launch_bounds__(RB) k_update(cplx<R>* __restrict__ w, const cp
         nrm += orr * orr + oi * oi;
     }
     if (!partial) return;
-    red[threadIdx.x] = nrm;
-    tree_reduce(red, 1);
-    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * S.B + c] = red[0];
+    double a[1] = {nrm};
+    const double t = block_sum(a, 1, red);
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * S.B + c] = t;
+}
+
+// The first Gram-Schmidt update fused with the second projection, for K
+// basis vectors: w' = w - sum_k coef[k][c] V_k (rounded to the state's
+// precision, as stored), and partial[bx][k][c] = sum over this workgroup's rows
+// of conj(V_k[r,c]) w'[r,c].  Each V_k[r] is read once for both uses.
+template <typename R, int K>
+__global__ void __launch_bounds__(RB) k_update_dot(cplx<R>* __restrict__ w, const cplx<R>* __restrict__ V,
+                                                   int64_t vstride, const double* __restrict__ coef,
+                                                   Shape S, double* __restrict__ partial)
+{
+    __shared__ double red[kWaves * 2 * K];
+    const int c = blockIdx.y;
+    const int64_t col = (int64_t)c * S.D;
+    double cr[K], ci[K], a[2 * K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        cr[k] = coef[(k * S.B + c) * 2];
+        ci[k] = coef[(k * S.B + c) * 2 + 1];
+        a[2 * k] = a[2 * k + 1] = 0.0;
+    }
+    const int64_t step = (int64_t)gridDim.x * RB;
+    for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < S.D; r += step) {
+        const int64_t e = col + r;
+        const cplx<R> b = w[e];
+        cplx<R> v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = V[k * vstride + e];
+        double xr = b.re, xi = b.im;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            xr -= cr[k] * v[k].re - ci[k] * v[k].im;
+            xi -= cr[k] * v[k].im + ci[k] * v[k].re;
+        }
+        cplx<R> o;
+        o.re = (R)xr;
+        o.im = (R)xi;
+        w[e] = o;
+        const double orr = o.re, oi = o.im;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double vr = v[k].re, vi = v[k].im;
+            a[2 * k] += vr * orr + vi * oi;
+            a[2 * k + 1] += vr * oi - vi * orr;
+        }
+    }
+    const double t = block_sum(a, 2 * K, red);
+    if ((int)threadIdx.x < 2 * K)
+        partial[(((int64_t)blockIdx.x * K + (threadIdx.x >> 1)) * S.B + c) * 2 + (threadIdx.x & 1)] = t;
+}
+
+// The scalars of Lanczos iteration j for column b = thread: alpha_j =
+// Re(c1[j] + c2[j]) (the two projections on the newest basis vector), beta_j =
+// ||w||.  While the column is still growing its basis, its scale estimate
+// max_i (|alpha_i| + beta_{i-1}) is updated, and unless j is the last
+// iteration, beta_j at or below 1e-13 times that scale (or a zero start
+// vector) marks the subspace invariant (kdim = j + 1, f = 0); otherwise
+// f = 1 / beta_j scales w into the next basis vector.  A non-finite alpha or
+// beta sets flag[0].
+__global__ void k_lanczos_coef(const double* __restrict__ c1, const double* __restrict__ c2,
+                               const double* __restrict__ wnorm2, int j, int m, int B, double* __restrict__ alpha,
+                               double* __restrict__ beta, int* __restrict__ kdim, double* __restrict__ scale,
+                               const double* __restrict__ nrm, double* __restrict__ f, int* __restrict__ flag)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const double a = c1[((size_t)j * B + b) * 2] + c2[((size_t)j * B + b) * 2];
+    const double bt = sqrt(wnorm2[b]);
+    if (!isfinite(a) || !isfinite(bt)) flag[0] = 1;
+    alpha[(size_t)j * B + b] = a;
+    beta[(size_t)j * B + b] = bt;
+    double fb = 0.0;
+    if (j < kdim[b]) {
+        scale[b] = fmax(scale[b], fabs(a) + (j > 0 ? beta[(size_t)(j - 1) * B + b] : 0.0));
+        if (j < m - 1) {
+            if (bt <= 1e-13 * scale[b] || nrm[b] == 0.0) kdim[b] = j + 1;
+            else fb = 1.0 / bt;
+        }
+    }
+    f[b] = fb;
 }
 
 // Sum partial[g][i] over g < G in index order, for i < n doubles.
@@ -226,7 +329,19 @@ __global__ void __launch_bounds__(RB) k_combine(cplx<R>* __restrict__ y, const c
     for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < S.D; r += step) {
         const int64_t e = col + r;
         double xr = 0.0, xi = 0.0;
-        for (int k = 0; k < K; ++k) {
+        int k = 0;
+        for (; k + KC <= K; k += KC) {   // KC loads in flight, then their FMAs
+            cplx<R> v[KC];
+#pragma unroll
+            for (int u = 0; u < KC; ++u) v[u] = V[(k + u) * vstride + e];
+#pragma unroll
+            for (int u = 0; u < KC; ++u) {
+                const double cr = coef[((k + u) * S.B + c) * 2], ci = coef[((k + u) * S.B + c) * 2 + 1];
+                xr += cr * v[u].re - ci * v[u].im;
+                xi += cr * v[u].im + ci * v[u].re;
+            }
+        }
+        for (; k < K; ++k) {
             const double cr = coef[(k * S.B + c) * 2], ci = coef[(k * S.B + c) * 2 + 1];
             const cplx<R> v = V[k * vstride + e];
             xr += cr * v.re - ci * v.im;
@@ -297,32 +412,70 @@ void VecOps::majorana_sector(int a, int top, int s_in, const void* in, void* out
     SYK_HIP(hipGetLastError());
 }
 
-std::vector<zd> VecOps::multidot(const void* V, int K, const void* w)
+const double* VecOps::multidot_dev(const void* V, int K, const void* w, const char* slot)
 {
     Shape S{dim_, nvec_};
     dim3 g = grid_of(S, true);
     const int B = nvec_;
-    std::vector<zd> res((size_t)K * B);
-    double* out = (double*)h_.ws.get("md_out", (size_t)K * B * 2 * sizeof(double));
+    double* out = (double*)h_.ws.get(slot, (size_t)std::max(K, kFusedMax) * B * 2 * sizeof(double));
     for (int k0 = 0; k0 < K; k0 += KC) {
         const int kk = std::min(KC, K - k0);
         double* part = (double*)h_.ws.get("md_part", (size_t)g.x * kk * B * 2 * sizeof(double));
         const size_t off = (size_t)k0 * vec_bytes();
-        if (dt_ == SYK_C128)
-            hipLaunchKernelGGL(k_multidot<double>, g, dim3(RB), 0, s_,
-                               (const c128*)((const char*)V + off), dim_ * B, kk, (const c128*)w, S, part);
-        else
-            hipLaunchKernelGGL(k_multidot<float>, g, dim3(RB), 0, s_,
-                               (const c64*)((const char*)V + off), dim_ * B, kk, (const c64*)w, S, part);
+        with_count<KC>(kk, [&](auto kc) {
+            constexpr int K_ = decltype(kc)::value;
+            if (dt_ == SYK_C128)
+                hipLaunchKernelGGL((k_multidot<double, K_>), g, dim3(RB), 0, s_,
+                                   (const c128*)((const char*)V + off), dim_ * B, (const c128*)w, S, part);
+            else
+                hipLaunchKernelGGL((k_multidot<float, K_>), g, dim3(RB), 0, s_,
+                                   (const c64*)((const char*)V + off), dim_ * B, (const c64*)w, S, part);
+        });
         SYK_HIP(hipGetLastError());
         const int n = kk * B * 2;
         hipLaunchKernelGGL(k_finish, dim3((n + 255) / 256), dim3(256), 0, s_, part, (int)g.x, n,
                            out + (size_t)k0 * B * 2);
         SYK_HIP(hipGetLastError());
     }
-    std::vector<double> flat = download<double>(out, (size_t)K * B * 2);
-    for (size_t i = 0; i < res.size(); ++i) res[i] = zd(flat[2 * i], flat[2 * i + 1]);
+    return out;
+}
+
+std::vector<zd> VecOps::fetch(const double* dev, int K)
+{
+    const size_t n = (size_t)K * nvec_;
+    std::vector<double> flat = download<double>(dev, 2 * n);
+    std::vector<zd> res(n);
+    for (size_t i = 0; i < n; ++i) res[i] = zd(flat[2 * i], flat[2 * i + 1]);
     return res;
+}
+
+std::vector<zd> VecOps::multidot(const void* V, int K, const void* w)
+{
+    return fetch(multidot_dev(V, K, w, "md_out"), K);
+}
+
+const double* VecOps::update_dot(void* w, const void* V, int K, const double* c1, const char* slot)
+{
+    if (K < 1 || K > kFusedMax) throw Error(SYK_EINVAL, "update_dot: unsupported basis size");
+    Shape S{dim_, nvec_};
+    dim3 g = grid_of(S, true);
+    const int B = nvec_;
+    double* part = (double*)h_.ws.get("ud_part", (size_t)g.x * kFusedMax * B * 2 * sizeof(double));
+    double* out = (double*)h_.ws.get(slot, (size_t)kFusedMax * B * 2 * sizeof(double));
+    const int64_t vs = dim_ * B;
+    with_count<kFusedMax>(K, [&](auto kc) {
+        constexpr int K_ = decltype(kc)::value;
+        if (dt_ == SYK_C128)
+            hipLaunchKernelGGL((k_update_dot<double, K_>), g, dim3(RB), 0, s_, (c128*)w, (const c128*)V, vs, c1, S,
+                               part);
+        else
+            hipLaunchKernelGGL((k_update_dot<float, K_>), g, dim3(RB), 0, s_, (c64*)w, (const c64*)V, vs, c1, S, part);
+    });
+    SYK_HIP(hipGetLastError());
+    const int n = K * B * 2;
+    hipLaunchKernelGGL(k_finish, dim3((n + 255) / 256), dim3(256), 0, s_, part, (int)g.x, n, out);
+    SYK_HIP(hipGetLastError());
+    return out;
 }
 
 std::vector<double> VecOps::norm2(const void* a)
@@ -335,30 +488,74 @@ std::vector<double> VecOps::norm2(const void* a)
 
 std::vector<double> VecOps::update(void* w, const void* V, int K, const std::vector<zd>& coef, bool want_norm)
 {
+    return update_dev(w, V, K, (const double*)upload(coef), want_norm);
+}
+
+std::vector<double> VecOps::update_dev(void* w, const void* V, int K, const double* dcoef, bool want_norm)
+{
+    const double* n = update_dev_norm(w, V, K, dcoef, want_norm);
+    if (!want_norm) return {};
+    return download<double>(n, nvec_);
+}
+
+const double* VecOps::update_dev_norm(void* w, const void* V, int K, const double* dcoef, bool want_norm)
+{
     Shape S{dim_, nvec_};
     const int B = nvec_;
     dim3 g = grid_of(S, true);
-    std::vector<double> norms;
-    double* dcoef = (double*)upload(coef);
     double* part = want_norm ? (double*)h_.ws.get("up_part", (size_t)g.x * B * sizeof(double)) : nullptr;
     for (int k0 = 0; k0 < K; k0 += KC) {
         const int kk = std::min(KC, K - k0);
         const bool last = k0 + KC >= K;
         const size_t off = (size_t)k0 * vec_bytes();
         double* p = (last && want_norm) ? part : nullptr;
-        if (dt_ == SYK_C128)
-            hipLaunchKernelGGL(k_update<double>, g, dim3(RB), 0, s_, (c128*)w,
-                               (const c128*)((const char*)V + off), dim_ * B, kk, dcoef + (size_t)k0 * B * 2, S, p);
-        else
-            hipLaunchKernelGGL(k_update<float>, g, dim3(RB), 0, s_, (c64*)w,
-                               (const c64*)((const char*)V + off), dim_ * B, kk, dcoef + (size_t)k0 * B * 2, S, p);
+        with_count<KC>(kk, [&](auto kc) {
+            constexpr int K_ = decltype(kc)::value;
+            if (dt_ == SYK_C128)
+                hipLaunchKernelGGL((k_update<double, K_>), g, dim3(RB), 0, s_, (c128*)w,
+                                   (const c128*)((const char*)V + off), dim_ * B, dcoef + (size_t)k0 * B * 2, S, p);
+            else
+                hipLaunchKernelGGL((k_update<float, K_>), g, dim3(RB), 0, s_, (c64*)w,
+                                   (const c64*)((const char*)V + off), dim_ * B, dcoef + (size_t)k0 * B * 2, S, p);
+        });
         SYK_HIP(hipGetLastError());
     }
-    if (!want_norm) return norms;
+    if (!want_norm) return nullptr;
     double* out = (double*)h_.ws.get("up_out", (size_t)B * sizeof(double));
     hipLaunchKernelGGL(k_finish, dim3((B + 255) / 256), dim3(256), 0, s_, part, (int)g.x, B, out);
     SYK_HIP(hipGetLastError());
-    return download<double>(out, B);
+    return out;
+}
+
+void VecOps::lanczos_coef(const double* c1, const double* c2, const double* wnorm2, int j, int m, LanczosScalars& z)
+{
+    const int B = nvec_;
+    hipLaunchKernelGGL(k_lanczos_coef, dim3((B + 255) / 256), dim3(256), 0, s_, c1, c2, wnorm2, j, m, B, z.alpha,
+                       z.beta, z.kdim, z.scale, z.nrm, z.f, z.flag);
+    SYK_HIP(hipGetLastError());
+}
+
+void VecOps::scale_dev(void* out, const void* in, const double* df)
+{
+    Shape S{dim_, nvec_};
+    dim3 g = grid_of(S, false);
+    if (dt_ == SYK_C128)
+        hipLaunchKernelGGL(k_scale<double>, g, dim3(RB), 0, s_, (c128*)out, (const c128*)in, df, S);
+    else
+        hipLaunchKernelGGL(k_scale<float>, g, dim3(RB), 0, s_, (c64*)out, (const c64*)in, df, S);
+    SYK_HIP(hipGetLastError());
+}
+
+void VecOps::to_device(void* dev, const void* host, size_t bytes)
+{
+    SYK_HIP(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, s_));
+    SYK_HIP(hipStreamSynchronize(s_));
+}
+
+void VecOps::to_host(void* host, const void* dev, size_t bytes)
+{
+    SYK_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s_));
+    SYK_HIP(hipStreamSynchronize(s_));
 }
 
 void VecOps::scale(void* out, const void* in, const std::vector<double>& f)
