@@ -151,6 +151,35 @@ def test_krylov_breakdown_eigenvector():
     assert err[0] == 0.0
 
 
+def test_krylov_breakdown_mixed_block():
+    """One block whose columns reach an invariant subspace at different
+    Lanczos iterations (an eigenvector, sums of two and of three eigenvectors),
+    next to a generic state and a zero column: each column against the exact
+    exponential, with a zero error estimate where the space closed."""
+    N = 8
+    J = inputs.couplings(N, 0)
+    ev, evec = np.linalg.eigh(jw.dense_H(N, J))
+    rng = np.random.default_rng(5)
+    cols = [evec[:, 2],
+            evec[:, 1] + 0.5 * evec[:, 9],
+            evec[:, 0] - 0.3 * evec[:, 7] + 0.8j * evec[:, 14],
+            inputs.typical_state(N, 3),
+            np.zeros(evec.shape[0])]
+    blk = np.stack([np.asarray(c, dtype=np.complex128) for c in cols])
+    T = api.Terms(N, J)
+    x = _gpu(blk)
+    err = api.krylov_expmv(T, x, -1j, 0.9, m=12, dt=1.0)
+    got = x.cpu().numpy()
+    U = (evec * np.exp(-0.9j * ev)) @ evec.conj().T
+    for c in range(4):
+        ref = U @ blk[c]
+        assert np.abs(got[c] - ref).max() <= 1e-12 * np.abs(ref).max(), c
+    assert np.all(got[4] == 0)
+    assert err[0] == 0.0 and err[1] == 0.0 and err[2] == 0.0 and err[4] == 0.0
+    assert err[3] <= 1e-10
+    T.close()
+
+
 # ----------------------------------------------------------- correlators
 def test_two_point_cfg1():
     """N=16, beta=0, G(t) for t = 0:0.1:10 with m=20, checked against a dense
