@@ -60,6 +60,25 @@ def test_noalloc_equals_apply_two_calls_in_a_row():
         T.close()
 
 
+def test_noalloc_two_columns_per_workgroup():
+    """A complex64 block whose columns pair up by realisation runs two
+    columns per workgroup (the automatic shape): the allocation-free call
+    gives syk_apply_H's bits there too, at N = 36 (two row layouts)."""
+    N = 36
+    _say(f"N={N} complex64 nvec=4 paired")
+    Js = np.stack([inputs.couplings(N, 95 + r) for r in range(2)])
+    T = api.Terms(N, Js)
+    psi = _states(N, [11, 12, 13, 14], torch.complex64)
+    real = [1, 1, 0, 0]
+    ref = api.apply_H(T, psi, real_of_col=real)
+    torch.cuda.synchronize()
+    out = torch.full_like(psi, complex(float("nan"), float("nan")))
+    assert _raw(T, psi, out, real) == _lib.SYK_OK, _lib.lib().syk_last_error()
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    T.close()
+
+
 def test_noalloc_rejects_what_it_cannot_serve():
     # a handle that never ran syk_apply_H has no tables
     N = 36
