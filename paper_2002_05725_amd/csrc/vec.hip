@@ -292,14 +292,25 @@ __global__ void k_lanczos_coef(const double* __restrict__ c1, const double* __re
     f[b] = fb;
 }
 
-// Sum partial[g][i] over g < G in index order, for i < n doubles.
-__global__ void k_finish(const double* __restrict__ partial, int G, int n, double* __restrict__ out)
+// out[i] = sum of partial[g][i] over g < G, for i < n doubles: one wave per
+// output, lane l adding g = l, l + 64, ... in order, then a fixed butterfly
+// over the lanes (the same order on every run).
+__global__ void __launch_bounds__(64) k_finish(const double* __restrict__ partial, int G, int n,
+                                               double* __restrict__ out)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x;
     if (i >= n) return;
     double s = 0.0;
-    for (int g = 0; g < G; ++g) s += partial[(int64_t)g * n + i];
-    out[i] = s;
+    for (int g = (int)threadIdx.x; g < G; g += 64) s += partial[(int64_t)g * n + i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (threadIdx.x == 0) out[i] = s;
+}
+
+void launch_finish(const double* partial, int G, int n, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_finish, dim3(n), dim3(64), 0, st, partial, G, n, out);
+    SYK_HIP(hipGetLastError());
 }
 
 template <typename R>
@@ -433,8 +444,7 @@ const double* VecOps::multidot_dev(const void* V, int K, const void* w, const ch
         });
         SYK_HIP(hipGetLastError());
         const int n = kk * B * 2;
-        hipLaunchKernelGGL(k_finish, dim3((n + 255) / 256), dim3(256), 0, s_, part, (int)g.x, n,
-                           out + (size_t)k0 * B * 2);
+        launch_finish(part, (int)g.x, n, out + (size_t)k0 * B * 2, s_);
         SYK_HIP(hipGetLastError());
     }
     return out;
@@ -473,7 +483,7 @@ const double* VecOps::update_dot(void* w, const void* V, int K, const double* c1
     });
     SYK_HIP(hipGetLastError());
     const int n = K * B * 2;
-    hipLaunchKernelGGL(k_finish, dim3((n + 255) / 256), dim3(256), 0, s_, part, (int)g.x, n, out);
+    launch_finish(part, (int)g.x, n, out, s_);
     SYK_HIP(hipGetLastError());
     return out;
 }
@@ -522,7 +532,7 @@ const double* VecOps::update_dev_norm(void* w, const void* V, int K, const doubl
     }
     if (!want_norm) return nullptr;
     double* out = (double*)h_.ws.get("up_out", (size_t)B * sizeof(double));
-    hipLaunchKernelGGL(k_finish, dim3((B + 255) / 256), dim3(256), 0, s_, part, (int)g.x, B, out);
+    launch_finish(part, (int)g.x, B, out, s_);
     SYK_HIP(hipGetLastError());
     return out;
 }

@@ -4,6 +4,7 @@ Tolerances (complex128): relative 2-norm error <= 1e-10 for vectors, and
 max_t |dF| / max_t |F_ref| <= 1e-10 for correlator curves.  complex64:
 relative vector error <= 2e-6, |dF| <= 2e-5 against the complex128 path.
 """
+import os
 import sys
 
 import numpy as np
@@ -16,6 +17,7 @@ from paper_2002_05725_amd import api, inputs
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def _say(msg):
@@ -391,7 +393,7 @@ def test_batched_otoc_full_block_n36():
     x 2 typical states in one 64-column block, beta=5, t in [0, 12].  complex64
     block vs complex128 block to 2e-5 (FP64 inner products, complex64 states);
     a sampled column of the complex128 block vs a single-column call on its own
-    realisation (1e-12)."""
+    realisation (1e-12), and vs the checker's values at t = 0 and 6 (1e-10)."""
     N, R = 36, 32
     _say("batched OTOC block N=36, 64 columns")
     Js = np.stack([inputs.couplings(N, inputs.batch_coupling_seed(N, r)) for r in range(R)])
@@ -409,4 +411,12 @@ def test_batched_otoc_full_block_n36():
         assert np.abs(F[:, c] - Fc[:, 0]).max() <= 1e-12 * max(1.0, np.abs(Fc).max())
         assert abs(Z[c] - Zc[0]) <= 1e-12 * Zc[0]
         Tc.close()
+    # column 37 against the checker's values (tests/golden/make_block_n36.py:
+    # the same Lanczos parameters on its sparse H) at t = 0 and 6
+    g = np.loadtxt(os.path.join(GOLDEN, "block_n36_otoc.txt"))
+    for row in g:
+        k = times.index(float(row[0]))
+        assert abs(F[k, 37] - row[1]) <= 1e-10, (row[0], F[k, 37], row[1])
+        assert abs(F64[k, 37] - row[1]) <= 2e-5
+    assert abs(Z[37] - g[0, 3]) <= 1e-10 * g[0, 3]
     T.close()
