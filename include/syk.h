@@ -171,7 +171,9 @@ typedef struct {
  * otherwise; total >= 0 is cut into equal steps no longer than that.  A
  * Krylov space that becomes invariant ends the step early with the exact
  * result.  err_est (host, nvec, may be NULL) receives the largest step error
- * estimate beta_m |e_m^T e^{zT} e_1| ||psi|| per column.
+ * estimate beta_m |e_m^T e^{zT} e_1| ||psi|| per column.  With the environment
+ * variable SYK_PROGRESS set, every finished step is reported on stderr (here
+ * and in the estimators built on these steps).
  */
 syk_status syk_krylov_expmv(syk_terms t, syk_dtype dtype, int nvec, const int32_t* real_of_col,
                             double z_re, double z_im, double total, const syk_krylov_opts* opts,
@@ -336,7 +338,8 @@ syk_status syk_cheb_otoc(syk_terms t, int i, int j, double beta, double t_star, 
  * with states recomputed from checkpoints, and per-coupling reductions
  * Re <g| dH/dJ v> accumulated on the device.  Includes the derivative of
  * <psi|rho|psi>.  With the environment variable SYK_PROGRESS set, each
- * finished checkpoint segment of the reverse sweep is reported on stderr.
+ * finished checkpoint segment of the reverse sweep is reported on stderr (and
+ * every Krylov propagation step of any call, as for syk_krylov_expmv).
  */
 syk_status syk_grad_couplings(syk_terms t, int i, int j, double beta, double t_star, const syk_cheb_opts* opts,
                               const void* psi0, double* F, double* dF_dJ, hipStream_t stream);

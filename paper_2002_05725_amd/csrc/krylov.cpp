@@ -14,6 +14,8 @@
 #include <algorithm>
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 namespace syk {
 
@@ -195,7 +197,17 @@ void krylov_propagate(BlockCtx& c, void* psi, std::complex<double> z, double tot
     require(total > 0 && step > 0, "propagation length and step must be positive");
     const int n = std::max(1, (int)std::ceil(total / step - 1e-9));
     const double h = total / n;
-    for (int i = 0; i < n; ++i) krylov_step(c, psi, z * h, m, st);
+    // With SYK_PROGRESS set in the environment, every finished step is reported
+    // on stderr (each step has already read its Lanczos scalars back).
+    static const bool report = std::getenv("SYK_PROGRESS") != nullptr;
+    for (int i = 0; i < n; ++i) {
+        krylov_step(c, psi, z * h, m, st);
+        if (report) {
+            std::fprintf(stderr, "[syk] Krylov step %d/%d of exp((%g%+gi) H), %d column(s)\n", i + 1, n, h * z.real(),
+                         h * z.imag(), c.nvec);
+            std::fflush(stderr);
+        }
+    }
 }
 
 }  // namespace syk
