@@ -37,7 +37,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Vector-ALU roofs of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x
 # 2.4 GHz = 78.6 TFLOP/s in FP64; the published FP32 figure, 157.3 TFLOP/s,
-# counts packed FP32 FMAs (two per lane per instruction).  This build compiles
+# counts packed FP32 FMAs (two per lane per instruction).  The library compiles
 # without packed FP32, and non-packed FP32 FMAs issue at the FP64 rate (an FMA
 # throughput probe on the MI355X: 76.5 TFLOP/s), so the complex64 figures are
 # given against both.
@@ -115,7 +115,7 @@ def otoc_window(api, torch, T, x, times, beta, m, dt, tau, real=None):
     return F, Fi, wall, n / m, ms
 
 
-def cfg5_window_leg(api, torch, T, psi_host, dev, N):
+def beta10_window_leg(api, torch, T, psi_host, dev, N):
     """The N = 52 OTOC (beta J = 10, Lanczos m = 12, real step 0.25, imaginary
     step 0.625) on its first output window, t in {0, 0.5}, in complex128 and in
     complex64 (FP64 inner products) from the same typical state."""
@@ -384,7 +384,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the sharded design is described, not built)", file=sys.stderr)
         sys.exit(2)
 
@@ -502,7 +502,7 @@ def main():
     snap.clear()
     window = None
     if not args.no_window:
-        window = cfg5_window_leg(api, torch, T, psi_host, dev, N)
+        window = beta10_window_leg(api, torch, T, psi_host, dev, N)
         log(f"[bench] window: |dF| c64 vs c128 = {window['max_abs_dF_c64_vs_c128']:.2e}")
     sector = None
     if args.sector_steps > 0:

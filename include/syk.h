@@ -48,7 +48,7 @@ typedef enum {
     SYK_EHIP = 3,            /* HIP runtime error */
     SYK_EBREAKDOWN = 4,      /* non-finite norm inside a propagation */
     SYK_ENOTCONVERGED = 5,   /* a-posteriori error estimate above the requested tolerance */
-    SYK_EUNSUPPORTED = 6     /* valid request this build does not handle */
+    SYK_EUNSUPPORTED = 6     /* valid request the library does not handle */
 } syk_status;
 
 typedef enum { SYK_C128 = 0, SYK_C64 = 1 } syk_dtype;

@@ -1,4 +1,4 @@
-"""Writes cfg2_n32_otoc.txt: the CPU checker's regularized OTOC at N=32.
+"""Writes otoc_beta10_n32.txt: the CPU checker's regularized OTOC at N=32.
 
 Workload (regularized OTOC, main text Eq. 4, from one typical state as in the
 SI section "Disorder averaging"): N = 32 Majoranas (dim 65,536, 35,960
@@ -11,7 +11,7 @@ real-time step 0.5, imaginary-time step 0.625.  Both step sizes keep the
 Krylov error far below 1e-12 here, so a propagation with any finer step (the
 HIP path uses dt = 0.05) must agree to about that.  Only oracle/ is called.
 
-Run from the repository root:  python tests/golden/make_cfg2_n32.py
+Run from the repository root:  python tests/golden/make_otoc_beta10_n32.py
 (a few minutes on 8 cores).
 """
 import os
@@ -40,9 +40,9 @@ def main():
         F, Fi, Z = correlators.otoc_estimator(prop, maj, psi, 0, 1, BETA, [t])
         rows.append((t, F[0], Fi[0], Z))
         print(f"t={t}: F={F[0]!r} ({time.time() - t0:.0f} s)", flush=True)
-    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cfg2_n32_otoc.txt")
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "otoc_beta10_n32.txt")
     with open(out, "w") as f:
-        f.write("# t F F_im Z  (make_cfg2_n32.py: checker Lanczos m=30, dt=0.5, tau_step=0.625, "
+        f.write("# t F F_im Z  (make_otoc_beta10_n32.py: checker Lanczos m=30, dt=0.5, tau_step=0.625, "
                 "N=32, beta=10, couplings seed 0, state seed 1, i=0, j=1)\n")
         for r in rows:
             f.write(" ".join(repr(float(x)) for x in r) + "\n")

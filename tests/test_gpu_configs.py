@@ -4,7 +4,7 @@ modes, through the C-ABI, against the CPU checker.
 * Finite-beta G(t) (main text Eq. 2-3, typical state as in the SI section
   "Disorder averaging") in the full space against the checker's estimator.
 * The N = 32 OTOC (beta J = 10, Lanczos m = 30, dt = 0.05) out to t = 15
-  against checker values stored in tests/golden/cfg2_n32_otoc.txt, and its
+  against checker values stored in tests/golden/otoc_beta10_n32.txt, and its
   full 31-point grid t in [0, 15] at N = 20 against the checker directly.
 * The Lyapunov rescaling tool (main text "Lyapunov exponent of the SYK model";
   SI finite-size extrapolation) on OTOC curves the GPU produced, against the
@@ -68,11 +68,11 @@ def test_two_point_finite_beta_vs_checker(N, beta):
 
 
 # ------------------------------------------------- the N = 32 OTOC to t = 15
-def test_otoc_cfg2_n32_long_times():
+def test_otoc_beta10_n32_long_times():
     """N=32, beta J = 10, m = 30, dt = 0.05 on the GPU out to t = 15 against
-    the checker's values (tests/golden/make_cfg2_n32.py: its Lanczos on its
+    the checker's values (tests/golden/make_otoc_beta10_n32.py: its Lanczos on its
     sparse H with dt = 0.5, each time propagated from scratch)."""
-    rows = np.loadtxt(os.path.join(GOLDEN, "cfg2_n32_otoc.txt"))
+    rows = np.loadtxt(os.path.join(GOLDEN, "otoc_beta10_n32.txt"))
     times, Fr, Fir, Zr = rows[:, 0], rows[:, 1], rows[:, 2], rows[:, 3]
     N = 32
     _say("otoc N=32 to t=15")
@@ -85,7 +85,7 @@ def test_otoc_cfg2_n32_long_times():
     T.close()
 
 
-def test_otoc_cfg2_full_grid_n20():
+def test_otoc_beta10_full_grid_n20():
     """The N = 32 schedule's full output grid (t = 0, 0.5, ..., 15; beta J = 10;
     m = 30) at N = 20, where the checker can propagate every point from
     scratch: GPU (dt = 0.25) against the checker's Lanczos (dt = 0.5) on its

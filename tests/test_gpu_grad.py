@@ -156,7 +156,7 @@ def test_coupling_overlaps_vs_checker(N, count):
     T.close()
 
 
-def test_grad_vs_finite_differences_cfg4_schedule_n28():
+def test_grad_vs_finite_differences_t6_schedule_n28():
     """The gradient workload's full schedule (beta J = 5, t* = 6, Chebyshev
     degree 32, dt = 0.1, a checkpoint every 10 operations) at N = 28: 50
     couplings drawn as for the workload (seed 4, without replacement) against

@@ -183,7 +183,7 @@ def test_krylov_breakdown_mixed_block():
 
 
 # ----------------------------------------------------------- correlators
-def test_two_point_cfg1():
+def test_two_point_beta0_n16():
     """N=16, beta=0, G(t) for t = 0:0.1:10 with m=20, checked against a dense
     eigendecomposition on the same state."""
     N = 16
@@ -319,7 +319,7 @@ def test_ground_state_energy_n28_vs_checker():
     assert np.abs(res - res_ref[:4]).max() <= 1e-6 * max(res_ref[:4].max(), 1e-12) + 1e-12
 
 
-def test_otoc_cfg2_n32():
+def test_otoc_beta10_n32():
     """N=32, beta J = 10, Lanczos m=30, dt=0.05 on the GPU; the checker uses
     dt=0.5 on its sparse H (both converged to ~1e-12)."""
     N = 32
@@ -327,9 +327,9 @@ def test_otoc_cfg2_n32():
     psi = inputs.typical_state(N, 1)
     times = [0.0, 0.5, 1.0]
     T = api.Terms(N, J)
-    _say("otoc cfg2: GPU")
+    _say("otoc N=32 beta=10: GPU")
     F, Fi, Z = api.otoc(T, 0, 1, 10.0, times, _gpu(psi), m=30, dt=0.05, tau_step=0.625)
-    _say("otoc cfg2: checker (sparse H)")
+    _say("otoc N=32 beta=10: checker (sparse H)")
     sp = native.SparseH(N, J)
     prop = correlators.Propagator(sp, 30, 0.5, 0.625)
     maj = lambda a, v: native.majorana(N, a, v)
