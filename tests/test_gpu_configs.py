@@ -161,6 +161,37 @@ def test_overlapping_buffers_rejected():
     T.close()
 
 
+@pytest.mark.parametrize("N", [12, 36])
+def test_empty_requests_and_degenerate_values(N):
+    """Empty requests are rejected (no columns, no time points, descending
+    times, i == j); a propagation by zero leaves the state bit for bit; and at
+    beta = 0, t = 0 the estimators take their closed forms on any normalized
+    state: chi_i chi_j chi_i chi_j = -chi_i^2 chi_j^2 = -1/4 (i != j) gives
+    F = -1/4, chi_i^2 = 1/2 gives G = 1/2, and Z = 1."""
+    T = api.Terms(N, inputs.couplings(N, 0))
+    psi = inputs.typical_state(N, 1)
+    x = _gpu(psi)
+    y = torch.empty_like(x)
+    L = _lib.lib()
+    assert L.syk_apply_H(_raw_handle(T), _lib.SYK_C128, 0, None, ctypes.c_void_p(x.data_ptr()),
+                         ctypes.c_void_p(y.data_ptr()), None) == _lib.SYK_EINVAL
+    for bad in ([], [1.0, 0.5]):
+        with pytest.raises(_lib.SykError):
+            api.otoc(T, 0, 1, 0.0, bad, x)
+    with pytest.raises(_lib.SykError):
+        api.otoc(T, 2, 2, 0.0, [0.0], x)
+    z = x.clone()
+    api.krylov_expmv(T, z, -1j, 0.0)
+    assert torch.equal(z, x)
+    for dt, tol in ((torch.complex128, 1e-13), (torch.complex64, 1e-6)):
+        xs = _gpu(psi, dt)
+        F, Fi, Z = api.otoc(T, 0, 1, 0.0, [0.0], xs)
+        assert abs(F[0, 0] + 0.25) <= tol and abs(Fi[0, 0]) <= tol and abs(Z[0] - 1.0) <= 10 * tol
+        G, Zg = api.two_point(T, 3, 0.0, [0.0], xs)
+        assert abs(G[0, 0] - 0.5) <= tol and abs(Zg[0] - 1.0) <= 10 * tol
+    T.close()
+
+
 def test_nan_state_is_a_breakdown():
     N = 12
     T = api.Terms(N, inputs.couplings(N, 0))
