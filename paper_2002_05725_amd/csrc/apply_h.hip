@@ -75,6 +75,22 @@ __device__ __forceinline__ float flip(float x, uint32_t s) { return __int_as_flo
 
 __device__ __forceinline__ uint32_t bit(uint32_t r, uint32_t q) { return (r >> q) & 1u; }
 
+// Sign flip when the count c is odd: adding c << 31 to the word holding the
+// sign bit changes that bit exactly when c is odd.  Written as one
+// v_lshl_add_u32 per word (plain C lets the compiler share the shift between
+// words, one instruction more per table entry pair).
+__device__ __forceinline__ uint32_t add_lsb31(uint32_t w, uint32_t c)
+{
+    uint32_t r;
+    asm("v_lshl_add_u32 %0, %1, 31, %2" : "=v"(r) : "v"(c), "v"(w));
+    return r;
+}
+__device__ __forceinline__ double flip_odd(double x, uint32_t c)
+{
+    return __hiloint2double((int)add_lsb31((uint32_t)__double2hiint(x), c), __double2loint(x));
+}
+__device__ __forceinline__ float flip_odd(float x, uint32_t c) { return __uint_as_float(add_lsb31(__float_as_uint(x), c)); }
+
 // 4-bit QUAD table index: bit m = bit q_m of r.
 __device__ __forceinline__ uint32_t quad_index(uint32_t r, uint32_t qpack)
 {
@@ -138,6 +154,10 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
     constexpr uint32_t esz = sizeof(cplx<R>);
     // byte weights of the four gathered index bits: esz * 2^m
     constexpr uint32_t kDotW = (esz) | (2 * esz) << 8 | (4 * esz) << 16 | (8 * esz) << 24;
+    // kept in a VGPR, so that v_dot4 can take the per-mask table offset from an
+    // SGPR (one scalar operand per instruction)
+    uint32_t dotw = kDotW;
+    asm("" : "+v"(dotw));
     __shared__ ApplyLds<R, RPT, NC> S;
     constexpr uint32_t TS = RPT << kLaneBits;   // rows of a column's tile
     const char* src_b = reinterpret_cast<const char*>(S.src);
@@ -252,9 +272,9 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
                 for (uint32_t i = 0; i < n; ++i, mi += 3) {
                     const QRec q = qn;
                     if constexpr (kEarlyRecord) qn = rec[mi + 3];
-                    const uint32_t ia = __builtin_amdgcn_udot4(__builtin_amdgcn_perm(B1, B0, q.sel), kDotW,
+                    const uint32_t ia = __builtin_amdgcn_udot4(__builtin_amdgcn_perm(B1, B0, q.sel), dotw,
                                                                (mi - C.first) * 16u * esz, false);
-                    const uint32_t sl = (uint32_t)__popc(tid & q.zl) << 31;
+                    const uint32_t sl = (uint32_t)__popc(tid & q.zl);   // lane sign: its parity
                     const uint32_t kof = q.koffs;
                     auto load_member = [&](auto jc, cplx<R> (&t)[NE]) {
                         constexpr uint32_t j = decltype(jc)::value;
@@ -267,8 +287,8 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
                         constexpr int XK = group_xk(J, j), ZK = group_zk(XK, P);
 #pragma unroll
                         for (int e = 0; e < NE; ++e) {
-                            t[e].re = flip31(t[e].re, sl);
-                            t[e].im = flip31(t[e].im, sl);
+                            t[e].re = flip_odd(t[e].re, sl);
+                            t[e].im = flip_odd(t[e].im, sl);
                         }
 #pragma unroll
                         for (int c = 0; c < NC; ++c)
@@ -327,9 +347,9 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
             for (uint32_t i = 0; i < n; ++i, ++mi) {
                 const QRec q = qn;
                 if constexpr (kEarlyRecord) qn = rec[mi + 1];
-                const uint32_t ia = __builtin_amdgcn_udot4(__builtin_amdgcn_perm(B1, B0, q.sel), kDotW,
+                const uint32_t ia = __builtin_amdgcn_udot4(__builtin_amdgcn_perm(B1, B0, q.sel), dotw,
                                                            (mi - C.first) * 16u * esz, false);
-                const uint32_t sl = (uint32_t)__popc(tid & q.zl) << 31;
+                const uint32_t sl = (uint32_t)__popc(tid & q.zl);   // lane sign: its parity
                 cplx<R> te[RPT];   // entry for the k bits in p = k & XK
 #pragma unroll
                 for (int p = 0; p < RPT; ++p) {
@@ -353,8 +373,8 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
 #pragma unroll
                 for (int p = 0; p < RPT; ++p) {
                     if ((p & ~(int)XK) != 0) continue;
-                    te[p].re = flip31(te[p].re, sl);
-                    te[p].im = flip31(te[p].im, sl);
+                    te[p].re = flip_odd(te[p].re, sl);
+                    te[p].im = flip_odd(te[p].im, sl);
                 }
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
