@@ -155,9 +155,10 @@ k_apply(KTerms<R> T, const QApplyChunk* __restrict__ chunks,
     // byte weights of the four gathered index bits: esz * 2^m
     constexpr uint32_t kDotW = (esz) | (2 * esz) << 8 | (4 * esz) << 16 | (8 * esz) << 24;
     // kept in a VGPR, so that v_dot4 can take the per-mask table offset from an
-    // SGPR (one scalar operand per instruction)
+    // SGPR (one scalar operand per instruction); not for two complex64 columns,
+    // whose kernel is short of VGPRs at three waves (1.2% slower with it)
     uint32_t dotw = kDotW;
-    asm("" : "+v"(dotw));
+    if constexpr (NC == 1 || sizeof(R) == 8) asm("" : "+v"(dotw));
     __shared__ ApplyLds<R, RPT, NC> S;
     constexpr uint32_t TS = RPT << kLaneBits;   // rows of a column's tile
     const char* src_b = reinterpret_cast<const char*>(S.src);
